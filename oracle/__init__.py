@@ -1,0 +1,219 @@
+"""Reference oracle for staggered-grid leapfrog wave propagation.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The GPU library never
+calls into it, and it shares no code with the GPU library.
+
+The solver lives in ``oracle.c`` (plain C, fp64 evaluation with explicit
+rounding after every operation to emulate fp32/fp16/bf16 arithmetic); this
+module builds it with gcc, loads it with ctypes and wraps it for numpy.  The
+closed-form solutions are in ``closed_forms.py`` and the dense-operator
+construction in ``brute.py``.
+
+Formats: 'f64', 'f32', 'f16', 'bf16'.  Compensation: 'none', 'fast2sum'
+(Sec. 4, Code 1, three operations), 'twosum' (Sec. 4, Code 2, six operations).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FORMATS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+COMPS = {"none": 0, "fast2sum": 1, "twosum": 2}
+ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
+ACOUSTIC_FIELDS = ("vx", "vy", "p")
+
+# The compile line is part of the oracle's definition: no contraction of
+# a*b+c into fused multiply-adds, no fast-math value changes.
+CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+          "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it and return the path."""
+    if force or not os.path.exists(_LIB) or \
+            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        D = ctypes.c_double
+        Lg = ctypes.c_long
+        I = ctypes.c_int
+        P = ctypes.POINTER(ctypes.c_double)
+        PP = ctypes.POINTER(P)
+        L.orc_round.restype = D
+        L.orc_round.argtypes = [D, I]
+        L.orc_round_array.restype = None
+        L.orc_round_array.argtypes = [P, P, Lg, I]
+        L.orc_fast2sum.restype = None
+        L.orc_fast2sum.argtypes = [D, D, I, P, P]
+        L.orc_twosum.restype = None
+        L.orc_twosum.argtypes = [D, D, I, P, P]
+        L.orc_eft_check.restype = Lg
+        L.orc_eft_check.argtypes = [I, I, P, Lg, P, Lg, I]
+        L.orc_max_threads.restype = I
+        L.orc_max_threads.argtypes = []
+        L.orc_acoustic2d.restype = I
+        L.orc_acoustic2d.argtypes = [Lg, Lg, I, D, D, P, P, P, P, P, P, P, P,
+                                     I, I, I, Lg, Lg, P, I]
+        L.orc_acoustic2d_energy.restype = D
+        L.orc_acoustic2d_energy.argtypes = [Lg, Lg, I, D, D, P, P, P, P, P]
+        L.orc_elastic3d.restype = I
+        L.orc_elastic3d.argtypes = [Lg, Lg, Lg, D, D, P, P, P, PP, PP,
+                                    I, I, I, Lg, Lg, P, I]
+        L.orc_elastic3d_energy.restype = D
+        L.orc_elastic3d_energy.argtypes = [Lg, Lg, Lg, D, D, P, P, P, PP]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != shape:
+        a = np.ascontiguousarray(np.broadcast_to(a, shape), dtype=np.float64)
+    return a
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+# ---------------------------------------------------------------- formats --
+
+def round_to(x, fmt: str) -> np.ndarray:
+    """Round each value to the nearest value of `fmt` (ties to even)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    y = np.empty_like(x)
+    lib().orc_round_array(_ptr(x), _ptr(y), x.size, FORMATS[fmt])
+    return y
+
+
+def fast2sum(a: float, b: float, fmt: str):
+    s, t = ctypes.c_double(), ctypes.c_double()
+    lib().orc_fast2sum(a, b, FORMATS[fmt], ctypes.byref(s), ctypes.byref(t))
+    return s.value, t.value
+
+
+def twosum(a: float, b: float, fmt: str):
+    s, t = ctypes.c_double(), ctypes.c_double()
+    lib().orc_twosum(a, b, FORMATS[fmt], ctypes.byref(s), ctypes.byref(t))
+    return s.value, t.value
+
+
+def eft_check(fmt: str, which: int, a, b, require_order: bool) -> int:
+    """Number of pairs (a_i, b_j) whose compensated sum is not error free."""
+    a = _f64(a, np.shape(a))
+    b = _f64(b, np.shape(b))
+    return int(lib().orc_eft_check(FORMATS[fmt], which, _ptr(a), a.size,
+                                   _ptr(b), b.size, int(require_order)))
+
+
+# ---------------------------------------------------------------- solvers --
+
+def acoustic2d(nx, ny, order, dx, dt, rho, kappa, fields, *, storage="f64",
+               stencil="f64", comp="none", comps=None, nsteps=0,
+               energy_every=0, nthreads=0):
+    """Advance the 2D acoustic system (Eq. 1) by nsteps leapfrog steps.
+
+    fields: dict with 'vx', 'vy', 'p' ([ny, nx] arrays holding values of the
+    storage format, state (v^{n-1/2}, p^n)); comps: same keys for the
+    compensation terms (zeros if None).  rho, kappa at p points.
+    Returns (fields, comps, energy) with energy[m] = E at step m*energy_every.
+    """
+    shape = (ny, nx)
+    rho = _f64(rho, shape)
+    kappa = _f64(kappa, shape)
+    f = {k: _f64(fields[k], shape).copy() for k in ACOUSTIC_FIELDS}
+    if comp != "none":
+        c = {k: (_f64(comps[k], shape).copy() if comps is not None
+                 else np.zeros(shape)) for k in ACOUSTIC_FIELDS}
+    else:
+        c = {k: None for k in ACOUSTIC_FIELDS}
+    ne = nsteps // energy_every + 1 if energy_every > 0 else 0
+    energy = np.zeros(max(ne, 1))
+    rc = lib().orc_acoustic2d(nx, ny, order, dx, dt, _ptr(rho), _ptr(kappa),
+                              _ptr(f["vx"]), _ptr(f["vy"]), _ptr(f["p"]),
+                              _ptr(c["vx"]), _ptr(c["vy"]), _ptr(c["p"]),
+                              FORMATS[storage], FORMATS[stencil], COMPS[comp],
+                              nsteps, energy_every, _ptr(energy), nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the acoustic2d arguments")
+    return f, c, energy[:ne]
+
+
+def acoustic2d_energy(nx, ny, order, dx, dt, rho, kappa, fields) -> float:
+    shape = (ny, nx)
+    rho = _f64(rho, shape)
+    kappa = _f64(kappa, shape)
+    f = {k: _f64(fields[k], shape) for k in ACOUSTIC_FIELDS}
+    return float(lib().orc_acoustic2d_energy(
+        nx, ny, order, dx, dt, _ptr(rho), _ptr(kappa), _ptr(f["vx"]),
+        _ptr(f["vy"]), _ptr(f["p"])))
+
+
+def _ptr_array(arrs):
+    P = ctypes.POINTER(ctypes.c_double)
+    return (P * len(arrs))(*[_ptr(a) for a in arrs])
+
+
+def elastic3d(nx, ny, nz, dx, dt, rho, lam, mu, fields, *, storage="f64",
+              stencil="f64", comp="none", comps=None, nsteps=0,
+              energy_every=0, nthreads=0):
+    """Advance the 3D velocity-stress system by nsteps leapfrog steps.
+
+    fields: dict keyed by ELASTIC_FIELDS, [nz, ny, nx] arrays; material rho,
+    lambda, mu at cell centres.  Returns (fields, comps, energy).
+    """
+    shape = (nz, ny, nx)
+    rho, lam, mu = (_f64(a, shape) for a in (rho, lam, mu))
+    f = {k: _f64(fields[k], shape).copy() for k in ELASTIC_FIELDS}
+    if comp != "none":
+        c = {k: (_f64(comps[k], shape).copy() if comps is not None
+                 else np.zeros(shape)) for k in ELASTIC_FIELDS}
+        cptr = _ptr_array([c[k] for k in ELASTIC_FIELDS])
+    else:
+        c = {k: None for k in ELASTIC_FIELDS}
+        cptr = None
+    fptr = _ptr_array([f[k] for k in ELASTIC_FIELDS])
+    ne = nsteps // energy_every + 1 if energy_every > 0 else 0
+    energy = np.zeros(max(ne, 1))
+    rc = lib().orc_elastic3d(nx, ny, nz, dx, dt, _ptr(rho), _ptr(lam),
+                             _ptr(mu), fptr, cptr, FORMATS[storage],
+                             FORMATS[stencil], COMPS[comp], nsteps,
+                             energy_every, _ptr(energy), nthreads)
+    if rc != 0:
+        raise ValueError("oracle rejected the elastic3d arguments")
+    return f, c, energy[:ne]
+
+
+def elastic3d_energy(nx, ny, nz, dx, dt, rho, lam, mu, fields) -> float:
+    shape = (nz, ny, nx)
+    rho, lam, mu = (_f64(a, shape) for a in (rho, lam, mu))
+    f = {k: _f64(fields[k], shape) for k in ELASTIC_FIELDS}
+    return float(lib().orc_elastic3d_energy(
+        nx, ny, nz, dx, dt, _ptr(rho), _ptr(lam), _ptr(mu),
+        _ptr_array([f[k] for k in ELASTIC_FIELDS])))

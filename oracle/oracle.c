@@ -1,0 +1,691 @@
+/*
+ * oracle.c -- reference solver for staggered-grid leapfrog wave propagation
+ * with reduced-precision storage and compensated updates.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link, load or
+ * call this file; it exists so that tests, the smoke check and the CPU
+ * baseline leg of the benchmark can check the GPU library against a slow,
+ * plain implementation written directly from the paper.  It shares no code
+ * with the GPU library.
+ *
+ * What it computes (Gao & Harms, "Half precision wave simulation"):
+ *   - 2D acoustic system, Eq. (1) of Sec. 3, with the + signs as printed,
+ *     discretised on a staggered grid with the 4th-order staggered stencil
+ *     [1/24, -9/8, 9/8, -1/24] of Sec. 3 (or its 2nd-order [-1, 1] form),
+ *     periodic wrap in both directions, 2nd-order staggered leapfrog in time.
+ *   - The per-step procedure of Alg. 1 (plain update) and Alg. 2
+ *     (compensated update): all vx points, then all vy points, then all p
+ *     points; at each point stencil -> scale by the material -> update.
+ *   - The two compensated sums of Sec. 4: the 3-operation form (Code 1,
+ *     Fast2Sum) and the 6-operation form (Code 2, TwoSum).
+ *   - The 3D velocity-stress elastic system, the 3D extension of Eq. (A1)
+ *     of App. A, on the standard staggered (Virieux) layout.
+ *   - The discrete energy of the staggered leapfrog scheme (Sec. 3 uses it
+ *     as the diagnosis tool but defers its formula; the form used here is
+ *     derived from the scheme and conserved exactly in exact arithmetic).
+ *
+ * Precision emulation: every arithmetic operation is evaluated in double
+ * and then rounded to the precision it is specified in ("stencil" format
+ * for derivative/scaling arithmetic, "storage" format for the update).  An
+ * op on two p-bit numbers evaluated in double (53 bits >= 2p+2 for p <= 24)
+ * and then rounded to p bits equals the correctly rounded p-bit op, so this
+ * reproduces IEEE arithmetic in fp32, fp16 and bf16 (Table 1 lists the
+ * formats; bf16 has 8 significand bits and the fp32 exponent range).  With
+ * the storage and stencil formats set to fp64 nothing is rounded and the
+ * solver is the plain FP64 reference.
+ *
+ * Readings of the paper that are not fixed by its text (they are the ones
+ * the GPU library implements as well):
+ *   - Grid: p[j][i] at (i, j), vx[j][i] at (i+1/2, j), vy[j][i] at (i, j+1/2);
+ *     arrays row-major [ny][nx], x fastest.  State at the top of a step is
+ *     (v^{n-1/2}, p^n).
+ *   - dt and dx are folded into the stencil weights w_k = fp32(c_k*(dt/dx)).
+ *   - Material enters as b = fp32(1/rho) and kappa = fp32(kappa) at p points
+ *     (kappa = 1/beta); staggered buoyancy is the mean of the two adjacent b.
+ *     Scaling multiplies by b instead of dividing by rho.
+ *   - Compensation is added after scaling: y = RN_T(inc + c), then the
+ *     compensated sum of (v, y) gives the new (v, c).
+ *   - The stencil is evaluated in fp32 from the stored values.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { FMT_F64 = 0, FMT_F32 = 1, FMT_F16 = 2, FMT_BF16 = 3 };
+enum { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Rounding to a binary floating-point format (Sec. 2, Table 1).            */
+/* ------------------------------------------------------------------------ */
+
+/* Round x to the nearest number with `prec` significand bits (hidden bit
+ * included), smallest normal exponent `emin` (subnormals are kept: below
+ * 2^emin the spacing stays 2^(emin-prec+1)) and largest finite value
+ * `maxfin`; ties go to the even neighbour, magnitudes that round beyond
+ * maxfin become infinity. */
+static double round_to_format(double x, int prec, int emin, double maxfin)
+{
+    if (x == 0.0 || isnan(x) || isinf(x))
+        return x;
+    int e;
+    frexp(x, &e);               /* x = m * 2^e with 0.5 <= |m| < 1 */
+    int lead = e - 1;           /* exponent of the leading bit */
+    if (lead < emin)
+        lead = emin;
+    double quantum = ldexp(1.0, lead - prec + 1);
+    double r = nearbyint(x / quantum) * quantum; /* x/quantum is exact */
+    if (fabs(r) > maxfin)
+        r = copysign(INFINITY, x);
+    return r;
+}
+
+double orc_round(double x, int fmt)
+{
+    switch (fmt) {
+    case FMT_F32:
+        return round_to_format(x, 24, -126, 0x1.fffffep127);
+    case FMT_F16:
+        return round_to_format(x, 11, -14, 65504.0);
+    case FMT_BF16:
+        return round_to_format(x, 8, -126, 0x1.fep127);
+    default:
+        return x;
+    }
+}
+
+void orc_round_array(const double *x, double *y, long n, int fmt)
+{
+    for (long i = 0; i < n; ++i)
+        y[i] = orc_round(x[i], fmt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compensated sums (Sec. 4, Code 1 and Code 2), in format fmt.             */
+/* ------------------------------------------------------------------------ */
+
+/* 3-operation form: the sum s and the part t of b lost in forming it.
+ * Error free when |a| >= |b|. */
+void orc_fast2sum(double a, double b, int fmt, double *s, double *t)
+{
+    double ss = orc_round(a + b, fmt);
+    double z = orc_round(ss - a, fmt);
+    *t = orc_round(b - z, fmt);
+    *s = ss;
+}
+
+/* 6-operation form: error free for any ordering of |a| and |b|. */
+void orc_twosum(double a, double b, int fmt, double *s, double *t)
+{
+    double ss = orc_round(a + b, fmt);
+    double pa = orc_round(ss - b, fmt);
+    double pb = orc_round(ss - pa, fmt);
+    double da = orc_round(a - pa, fmt);
+    double db = orc_round(b - pb, fmt);
+    *t = orc_round(da + db, fmt);
+    *s = ss;
+}
+
+/* Exactness check used by the tests: counts pairs (a[i], b[j]) with
+ * a + b != s + t.  Equality of two exact sums of doubles is decided by
+ * comparing their canonical double-double forms (fp64 TwoSum yields the
+ * rounded sum and the exact remainder), which is exact for all the formats
+ * here because their values are multiples of 2^-149.  Pairs for which one
+ * of the operations overflows (s or t not finite) are skipped: near the top
+ * of the range s - b may round to infinity.  If require_order is set, only
+ * pairs with |a| >= |b| are checked. */
+long orc_eft_check(int fmt, int which, const double *a, long na,
+                   const double *b, long nb, int require_order)
+{
+    long bad = 0;
+    for (long i = 0; i < na; ++i) {
+        for (long j = 0; j < nb; ++j) {
+            double x = a[i], y = b[j];
+            if (require_order && fabs(x) < fabs(y))
+                continue;
+            double s, t;
+            if (which == 3)
+                orc_fast2sum(x, y, fmt, &s, &t);
+            else
+                orc_twosum(x, y, fmt, &s, &t);
+            if (!isfinite(s) || !isfinite(t))
+                continue;   /* an operation overflowed: no finite split */
+            double h1, l1, h2, l2;
+            orc_twosum(x, y, FMT_F64, &h1, &l1);
+            orc_twosum(s, t, FMT_F64, &h2, &l2);
+            if (h1 != h2 || l1 != l2)
+                ++bad;
+        }
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shared pieces of the solvers.                                            */
+/* ------------------------------------------------------------------------ */
+
+static long wrap(long i, long n)
+{
+    return ((i % n) + n) % n;
+}
+
+typedef struct {
+    int sf;    /* format of stencil and scaling arithmetic */
+    int tf;    /* storage format of fields and compensation terms */
+    int comp;  /* COMP_NONE / COMP_FAST2SUM / COMP_TWOSUM */
+} arith;
+
+/* Solution update of Alg. 1 (plain, V += R with R held in the storage
+ * format) and Alg. 2 (compensated, R carries the bits lost last time). */
+static void update(const arith *A, double *v, double *c, double inc)
+{
+    if (A->comp == COMP_NONE) {
+        double r = orc_round(inc, A->tf);
+        *v = orc_round(*v + r, A->tf);
+        return;
+    }
+    double y = orc_round(orc_round(inc + *c, A->sf), A->tf);
+    double s, t;
+    if (A->comp == COMP_FAST2SUM)
+        orc_fast2sum(*v, y, A->tf, &s, &t);
+    else
+        orc_twosum(*v, y, A->tf, &s, &t);
+    *v = s;
+    *c = t;
+}
+
+/* Neumaier's compensated summation in fp64, used for the energy. */
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double f32v(double x) { return orc_round(x, FMT_F32); }
+
+/* Stencil coefficients of the staggered first derivative (Sec. 3): order 4
+ * uses 9/8 and -1/24 (Levander), order 2 uses 1. */
+static void weights(int order, double dt, double dx, double *w1, double *w2)
+{
+    double r = dt / dx;
+    if (order == 4) {
+        *w1 = f32v((9.0 / 8.0) * r);
+        *w2 = f32v((-1.0 / 24.0) * r);
+    } else {
+        *w1 = f32v(1.0 * r);
+        *w2 = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2D acoustic.                                                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    long nx, ny;
+    int order;
+    double w1, w2;
+    double *b, *k;   /* fp32-valued buoyancy 1/rho and modulus kappa */
+} ac2d;
+
+#define IX(j, i) (wrap((j), G->ny) * G->nx + wrap((i), G->nx))
+
+static void ac2d_setup(ac2d *G, long nx, long ny, int order, double dx,
+                       double dt, const double *rho, const double *kappa)
+{
+    G->nx = nx;
+    G->ny = ny;
+    G->order = order;
+    weights(order, dt, dx, &G->w1, &G->w2);
+    long n = nx * ny;
+    G->b = malloc(sizeof(double) * n);
+    G->k = malloc(sizeof(double) * n);
+    for (long i = 0; i < n; ++i) {
+        G->b[i] = f32v(1.0 / rho[i]);
+        G->k[i] = f32v(kappa[i]);
+    }
+}
+
+static void ac2d_free(ac2d *G)
+{
+    free(G->b);
+    free(G->k);
+}
+
+/* One leapfrog step: v^{n-1/2} -> v^{n+1/2} from p^n, then p^n -> p^{n+1}
+ * from v^{n+1/2}.  In place, as in Alg. 1/2: the velocity loops read only
+ * p, and the pressure loop reads only the new velocities and p itself. */
+static void ac2d_step(const ac2d *G, const arith *A, double *vx, double *vy,
+                      double *p, double *cvx, double *cvy, double *cp)
+{
+    const int sf = A->sf;
+    const long nx = G->nx, ny = G->ny;
+    const double w1 = G->w1, w2 = G->w2;
+#define S(x) orc_round((x), sf)
+
+    /* vx at (i+1/2, j): dp/dx */
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+            double a0 = S(p[IX(j, i + 1)] - p[IX(j, i)]);
+            double g;
+            if (G->order == 4) {
+                double a1 = S(p[IX(j, i + 2)] - p[IX(j, i - 1)]);
+                g = S(S(w1 * a0) + S(w2 * a1));
+            } else {
+                g = S(w1 * a0);
+            }
+            double bx = S(0.5 * S(G->b[IX(j, i)] + G->b[IX(j, i + 1)]));
+            double inc = S(bx * g);
+            long q = j * nx + i;
+            update(A, &vx[q], cvx ? &cvx[q] : NULL, inc);
+        }
+
+    /* vy at (i, j+1/2): dp/dy */
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+            double a0 = S(p[IX(j + 1, i)] - p[IX(j, i)]);
+            double g;
+            if (G->order == 4) {
+                double a1 = S(p[IX(j + 2, i)] - p[IX(j - 1, i)]);
+                g = S(S(w1 * a0) + S(w2 * a1));
+            } else {
+                g = S(w1 * a0);
+            }
+            double by = S(0.5 * S(G->b[IX(j, i)] + G->b[IX(j + 1, i)]));
+            double inc = S(by * g);
+            long q = j * nx + i;
+            update(A, &vy[q], cvy ? &cvy[q] : NULL, inc);
+        }
+
+    /* p at (i, j): dvx/dx + dvy/dy */
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+            double ax0 = S(vx[IX(j, i)] - vx[IX(j, i - 1)]);
+            double ay0 = S(vy[IX(j, i)] - vy[IX(j - 1, i)]);
+            double gx, gy;
+            if (G->order == 4) {
+                double ax1 = S(vx[IX(j, i + 1)] - vx[IX(j, i - 2)]);
+                double ay1 = S(vy[IX(j + 1, i)] - vy[IX(j - 2, i)]);
+                gx = S(S(w1 * ax0) + S(w2 * ax1));
+                gy = S(S(w1 * ay0) + S(w2 * ay1));
+            } else {
+                gx = S(w1 * ax0);
+                gy = S(w1 * ay0);
+            }
+            double d = S(gx + gy);
+            long q = j * nx + i;
+            double inc = S(G->k[q] * d);
+            update(A, &p[q], cp ? &cp[q] : NULL, inc);
+        }
+#undef S
+}
+
+/* Discrete energy of the state (v^{n-1/2}, p^n), in fp64:
+ *   E^n = dx*dy/2 * sum[ p^2/kappa + vx^- vx^+ / bx + vy^- vy^+ / by ],
+ * where v^+ = v^{n+1/2} is recomputed exactly in fp64 from the state.  Per
+ * point the terms are formed in the order written; the sum over points is
+ * compensated. */
+static double ac2d_energy(const ac2d *G, double dx, const double *vx,
+                          const double *vy, const double *p)
+{
+    const long nx = G->nx, ny = G->ny;
+    const double w1 = G->w1, w2 = G->w2;
+    double *rows = malloc(sizeof(double) * 2 * ny);
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < ny; ++j) {
+        nsum acc = {0.0, 0.0};
+        for (long i = 0; i < nx; ++i) {
+            long q = j * nx + i;
+            double gx = w1 * (p[IX(j, i + 1)] - p[IX(j, i)]);
+            double gy = w1 * (p[IX(j + 1, i)] - p[IX(j, i)]);
+            if (G->order == 4) {
+                gx = gx + w2 * (p[IX(j, i + 2)] - p[IX(j, i - 1)]);
+                gy = gy + w2 * (p[IX(j + 2, i)] - p[IX(j - 1, i)]);
+            }
+            double bx = 0.5 * (G->b[q] + G->b[IX(j, i + 1)]);
+            double by = 0.5 * (G->b[q] + G->b[IX(j + 1, i)]);
+            double vxp = vx[q] + bx * gx;
+            double vyp = vy[q] + by * gy;
+            double e = (p[q] * p[q]) / G->k[q] + (vx[q] * vxp) / bx;
+            e = e + (vy[q] * vyp) / by;
+            nsum_add(&acc, e);
+        }
+        rows[2 * j] = acc.s;
+        rows[2 * j + 1] = acc.c;
+    }
+    nsum tot = {0.0, 0.0};
+    for (long j = 0; j < ny; ++j) {
+        nsum_add(&tot, rows[2 * j]);
+        nsum_add(&tot, rows[2 * j + 1]);
+    }
+    free(rows);
+    return 0.5 * dx * dx * (tot.s + tot.c);
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Run nsteps leapfrog steps of the 2D acoustic system in place.
+ * Fields vx, vy, p (and the compensation arrays, which may be NULL when
+ * comp == COMP_NONE) hold values of the storage format on entry.  If
+ * energy_every > 0, energy[m] receives E at step m*energy_every for
+ * m = 0 .. nsteps/energy_every.  Returns 0, or -1 on bad arguments. */
+int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
+                   const double *rho, const double *kappa, double *vx,
+                   double *vy, double *p, double *cvx, double *cvy,
+                   double *cp, int storage, int stencil, int comp,
+                   long nsteps, long energy_every, double *energy,
+                   int nthreads)
+{
+    if (nx < 1 || ny < 1 || (order != 2 && order != 4) || nsteps < 0)
+        return -1;
+    if (comp != COMP_NONE && (!cvx || !cvy || !cp))
+        return -1;
+    set_threads(nthreads);
+    ac2d G;
+    ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa);
+    arith A = {stencil, storage, comp};
+    long m = 0;
+    if (energy_every > 0)
+        energy[m++] = ac2d_energy(&G, dx, vx, vy, p);
+    for (long n = 1; n <= nsteps; ++n) {
+        ac2d_step(&G, &A, vx, vy, p, cvx, cvy, cp);
+        if (energy_every > 0 && n % energy_every == 0)
+            energy[m++] = ac2d_energy(&G, dx, vx, vy, p);
+    }
+    ac2d_free(&G);
+    return 0;
+}
+
+double orc_acoustic2d_energy(long nx, long ny, int order, double dx,
+                             double dt, const double *rho,
+                             const double *kappa, const double *vx,
+                             const double *vy, const double *p)
+{
+    ac2d G;
+    ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa);
+    double e = ac2d_energy(&G, dx, vx, vy, p);
+    ac2d_free(&G);
+    return e;
+}
+
+#undef IX
+
+/* ------------------------------------------------------------------------ */
+/* 3D elastic (velocity-stress), 2nd order.                                 */
+/*                                                                          */
+/* Layout (arrays [nz][ny][nx], x fastest):                                 */
+/*   sxx, syy, szz, material      at (i,     j,     k    )                  */
+/*   vx at (i+1/2, j, k), vy at (i, j+1/2, k), vz at (i, j, k+1/2)          */
+/*   sxy at (i+1/2, j+1/2, k), sxz at (i+1/2, j, k+1/2),                    */
+/*   syz at (i, j+1/2, k+1/2)                                               */
+/* Field order everywhere: vx, vy, vz, sxx, syy, szz, sxy, sxz, syz.        */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    long nx, ny, nz;
+    double w;
+    double *b, *lam, *mu;  /* fp32-valued 1/rho, lambda, mu at cells */
+} el3d;
+
+#define IX3(k, j, i)                                                      \
+    ((wrap((k), G->nz) * G->ny + wrap((j), G->ny)) * G->nx + wrap((i), G->nx))
+
+static void el3d_setup(el3d *G, long nx, long ny, long nz, double dx,
+                       double dt, const double *rho, const double *lam,
+                       const double *mu)
+{
+    G->nx = nx;
+    G->ny = ny;
+    G->nz = nz;
+    G->w = f32v(1.0 * (dt / dx));
+    long n = nx * ny * nz;
+    G->b = malloc(sizeof(double) * n);
+    G->lam = malloc(sizeof(double) * n);
+    G->mu = malloc(sizeof(double) * n);
+    for (long i = 0; i < n; ++i) {
+        G->b[i] = f32v(1.0 / rho[i]);
+        G->lam[i] = f32v(lam[i]);
+        G->mu[i] = f32v(mu[i]);
+    }
+}
+
+static void el3d_free(el3d *G)
+{
+    free(G->b);
+    free(G->lam);
+    free(G->mu);
+}
+
+static void el3d_step(const el3d *G, const arith *A, double *const *f,
+                      double *const *c)
+{
+    const int sf = A->sf;
+    const long nx = G->nx, ny = G->ny, nz = G->nz;
+    const double w = G->w;
+    double *vx = f[0], *vy = f[1], *vz = f[2];
+    double *sxx = f[3], *syy = f[4], *szz = f[5];
+    double *sxy = f[6], *sxz = f[7], *syz = f[8];
+    const double *B = G->b, *L = G->lam, *M = G->mu;
+#define S(x) orc_round((x), sf)
+#define CP(a, q) ((a) ? &(a)[q] : NULL)
+
+    /* velocities: rho dv/dt = div sigma */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (long k = 0; k < nz; ++k)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                long q = (k * ny + j) * nx + i;
+                {   /* vx at (i+1/2, j, k) */
+                    double d1 = S(sxx[IX3(k, j, i + 1)] - sxx[IX3(k, j, i)]);
+                    double d2 = S(sxy[IX3(k, j, i)] - sxy[IX3(k, j - 1, i)]);
+                    double d3 = S(sxz[IX3(k, j, i)] - sxz[IX3(k - 1, j, i)]);
+                    double g = S(w * S(S(d1 + d2) + d3));
+                    double bb = S(0.5 * S(B[IX3(k, j, i)] + B[IX3(k, j, i + 1)]));
+                    update(A, &vx[q], CP(c[0], q), S(bb * g));
+                }
+                {   /* vy at (i, j+1/2, k) */
+                    double d1 = S(sxy[IX3(k, j, i)] - sxy[IX3(k, j, i - 1)]);
+                    double d2 = S(syy[IX3(k, j + 1, i)] - syy[IX3(k, j, i)]);
+                    double d3 = S(syz[IX3(k, j, i)] - syz[IX3(k - 1, j, i)]);
+                    double g = S(w * S(S(d1 + d2) + d3));
+                    double bb = S(0.5 * S(B[IX3(k, j, i)] + B[IX3(k, j + 1, i)]));
+                    update(A, &vy[q], CP(c[1], q), S(bb * g));
+                }
+                {   /* vz at (i, j, k+1/2) */
+                    double d1 = S(sxz[IX3(k, j, i)] - sxz[IX3(k, j, i - 1)]);
+                    double d2 = S(syz[IX3(k, j, i)] - syz[IX3(k, j - 1, i)]);
+                    double d3 = S(szz[IX3(k + 1, j, i)] - szz[IX3(k, j, i)]);
+                    double g = S(w * S(S(d1 + d2) + d3));
+                    double bb = S(0.5 * S(B[IX3(k, j, i)] + B[IX3(k + 1, j, i)]));
+                    update(A, &vz[q], CP(c[2], q), S(bb * g));
+                }
+            }
+
+    /* stresses: dsigma/dt = lambda tr(e) I + 2 mu e, e the strain rate */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (long k = 0; k < nz; ++k)
+        for (long j = 0; j < ny; ++j)
+            for (long i = 0; i < nx; ++i) {
+                long q = (k * ny + j) * nx + i;
+                double ex = S(w * S(vx[IX3(k, j, i)] - vx[IX3(k, j, i - 1)]));
+                double ey = S(w * S(vy[IX3(k, j, i)] - vy[IX3(k, j - 1, i)]));
+                double ez = S(w * S(vz[IX3(k, j, i)] - vz[IX3(k - 1, j, i)]));
+                double lam = L[q];
+                double l2m = S(lam + S(2.0 * M[q]));
+                update(A, &sxx[q], CP(c[3], q),
+                       S(S(l2m * ex) + S(lam * S(ey + ez))));
+                update(A, &syy[q], CP(c[4], q),
+                       S(S(l2m * ey) + S(lam * S(ex + ez))));
+                update(A, &szz[q], CP(c[5], q),
+                       S(S(l2m * ez) + S(lam * S(ex + ey))));
+                {   /* sxy at (i+1/2, j+1/2, k) */
+                    double a = S(vy[IX3(k, j, i + 1)] - vy[IX3(k, j, i)]);
+                    double bq = S(vx[IX3(k, j + 1, i)] - vx[IX3(k, j, i)]);
+                    double g = S(w * S(a + bq));
+                    double m = S(0.25 * S(S(M[IX3(k, j, i)] + M[IX3(k, j, i + 1)]) +
+                                          S(M[IX3(k, j + 1, i)] + M[IX3(k, j + 1, i + 1)])));
+                    update(A, &sxy[q], CP(c[6], q), S(m * g));
+                }
+                {   /* sxz at (i+1/2, j, k+1/2) */
+                    double a = S(vz[IX3(k, j, i + 1)] - vz[IX3(k, j, i)]);
+                    double bq = S(vx[IX3(k + 1, j, i)] - vx[IX3(k, j, i)]);
+                    double g = S(w * S(a + bq));
+                    double m = S(0.25 * S(S(M[IX3(k, j, i)] + M[IX3(k, j, i + 1)]) +
+                                          S(M[IX3(k + 1, j, i)] + M[IX3(k + 1, j, i + 1)])));
+                    update(A, &sxz[q], CP(c[7], q), S(m * g));
+                }
+                {   /* syz at (i, j+1/2, k+1/2) */
+                    double a = S(vz[IX3(k, j + 1, i)] - vz[IX3(k, j, i)]);
+                    double bq = S(vy[IX3(k + 1, j, i)] - vy[IX3(k, j, i)]);
+                    double g = S(w * S(a + bq));
+                    double m = S(0.25 * S(S(M[IX3(k, j, i)] + M[IX3(k, j + 1, i)]) +
+                                          S(M[IX3(k + 1, j, i)] + M[IX3(k + 1, j + 1, i)])));
+                    update(A, &syz[q], CP(c[8], q), S(m * g));
+                }
+            }
+#undef CP
+#undef S
+}
+
+/* Discrete energy of the elastic state (v^{n-1/2}, sigma^n), fp64:
+ *   E^n = dx^3/2 * sum[ v^- . v^+ / b  +  s_n^T C^{-1} s_n  +  s_ij^2 / mu_ij ]
+ * with C = lambda 1 1^T + 2 mu I on the normal stresses, so
+ *   s_n^T C^{-1} s_n = (|s_n|^2 - lambda/(3 lambda + 2 mu) (tr s)^2) / (2 mu). */
+static double el3d_energy(const el3d *G, double dx, double *const *f)
+{
+    const long nx = G->nx, ny = G->ny, nz = G->nz;
+    const double w = G->w;
+    const double *vx = f[0], *vy = f[1], *vz = f[2];
+    const double *sxx = f[3], *syy = f[4], *szz = f[5];
+    const double *sxy = f[6], *sxz = f[7], *syz = f[8];
+    const double *B = G->b, *L = G->lam, *M = G->mu;
+    long nrows = ny * nz;
+    double *rows = malloc(sizeof(double) * 2 * nrows);
+#pragma omp parallel for schedule(static)
+    for (long r = 0; r < nrows; ++r) {
+        long k = r / ny, j = r % ny;
+        nsum acc = {0.0, 0.0};
+        for (long i = 0; i < nx; ++i) {
+            long q = (k * ny + j) * nx + i;
+            double gx = w * ((sxx[IX3(k, j, i + 1)] - sxx[IX3(k, j, i)]) +
+                             (sxy[q] - sxy[IX3(k, j - 1, i)]) +
+                             (sxz[q] - sxz[IX3(k - 1, j, i)]));
+            double gy = w * ((sxy[q] - sxy[IX3(k, j, i - 1)]) +
+                             (syy[IX3(k, j + 1, i)] - syy[q]) +
+                             (syz[q] - syz[IX3(k - 1, j, i)]));
+            double gz = w * ((sxz[q] - sxz[IX3(k, j, i - 1)]) +
+                             (syz[q] - syz[IX3(k, j - 1, i)]) +
+                             (szz[IX3(k + 1, j, i)] - szz[q]));
+            double bx = 0.5 * (B[q] + B[IX3(k, j, i + 1)]);
+            double by = 0.5 * (B[q] + B[IX3(k, j + 1, i)]);
+            double bz = 0.5 * (B[q] + B[IX3(k + 1, j, i)]);
+            double vxp = vx[q] + bx * gx;
+            double vyp = vy[q] + by * gy;
+            double vzp = vz[q] + bz * gz;
+            double ev = (vx[q] * vxp) / bx + (vy[q] * vyp) / by;
+            ev = ev + (vz[q] * vzp) / bz;
+            double lam = L[q], mu = M[q];
+            double tr = (sxx[q] + syy[q]) + szz[q];
+            double sq = (sxx[q] * sxx[q] + syy[q] * syy[q]) + szz[q] * szz[q];
+            double en = (sq - (lam / (3.0 * lam + 2.0 * mu)) * (tr * tr)) /
+                        (2.0 * mu);
+            double mxy = 0.25 * ((M[q] + M[IX3(k, j, i + 1)]) +
+                                 (M[IX3(k, j + 1, i)] + M[IX3(k, j + 1, i + 1)]));
+            double mxz = 0.25 * ((M[q] + M[IX3(k, j, i + 1)]) +
+                                 (M[IX3(k + 1, j, i)] + M[IX3(k + 1, j, i + 1)]));
+            double myz = 0.25 * ((M[q] + M[IX3(k, j + 1, i)]) +
+                                 (M[IX3(k + 1, j, i)] + M[IX3(k + 1, j + 1, i)]));
+            double es = (sxy[q] * sxy[q]) / mxy + (sxz[q] * sxz[q]) / mxz;
+            es = es + (syz[q] * syz[q]) / myz;
+            nsum_add(&acc, (ev + en) + es);
+        }
+        rows[2 * r] = acc.s;
+        rows[2 * r + 1] = acc.c;
+    }
+    nsum tot = {0.0, 0.0};
+    for (long r = 0; r < nrows; ++r) {
+        nsum_add(&tot, rows[2 * r]);
+        nsum_add(&tot, rows[2 * r + 1]);
+    }
+    free(rows);
+    return 0.5 * dx * dx * dx * (tot.s + tot.c);
+}
+
+/* Run nsteps of the 3D elastic system in place.  fields[9] and comps[9]
+ * (comps may be NULL when comp == COMP_NONE) are [nz][ny][nx] arrays in the
+ * field order above; material is rho, lambda, mu at cell centres. */
+int orc_elastic3d(long nx, long ny, long nz, double dx, double dt,
+                  const double *rho, const double *lam, const double *mu,
+                  double *const *fields, double *const *comps, int storage,
+                  int stencil, int comp, long nsteps, long energy_every,
+                  double *energy, int nthreads)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nsteps < 0)
+        return -1;
+    double *none[9] = {0};
+    if (comp != COMP_NONE) {
+        if (!comps)
+            return -1;
+        for (int f = 0; f < 9; ++f)
+            if (!comps[f])
+                return -1;
+    } else {
+        comps = none;
+    }
+    set_threads(nthreads);
+    el3d G;
+    el3d_setup(&G, nx, ny, nz, dx, dt, rho, lam, mu);
+    arith A = {stencil, storage, comp};
+    long m = 0;
+    if (energy_every > 0)
+        energy[m++] = el3d_energy(&G, dx, fields);
+    for (long n = 1; n <= nsteps; ++n) {
+        el3d_step(&G, &A, fields, comps);
+        if (energy_every > 0 && n % energy_every == 0)
+            energy[m++] = el3d_energy(&G, dx, fields);
+    }
+    el3d_free(&G);
+    return 0;
+}
+
+double orc_elastic3d_energy(long nx, long ny, long nz, double dx, double dt,
+                            const double *rho, const double *lam,
+                            const double *mu, double *const *fields)
+{
+    el3d G;
+    el3d_setup(&G, nx, ny, nz, dx, dt, rho, lam, mu);
+    double e = el3d_energy(&G, dx, fields);
+    el3d_free(&G);
+    return e;
+}
+
+#undef IX3

@@ -1,0 +1,256 @@
+"""Seeded synthetic inputs for the wave-propagation workloads.
+
+This module only draws inputs: initial fields, material models, batch and
+request mixes.  It holds none of the numerical method's arithmetic and is the
+one piece of code that both the oracle-side tests and the GPU-side callers
+use.  Every generator takes an explicit seed; the same seed gives the same
+arrays on every machine (numpy's PCG64 via default_rng).
+
+Workloads (sizes are the ones the paper's experiments and the benchmark use;
+the paper's own elastic medium is a dataset that is not available, so the
+smooth random medium below stands in for it):
+
+  small2d   2D acoustic, order 2, 128x128 periodic, rho = c = 1, dx = 1,
+            CFL 0.5, Gaussian pressure pulse (sigma 8 cells) at the centre,
+            zero velocity.
+  layered2d 2D acoustic, order 4, 4096x4096 periodic, 4 horizontal layers
+            (c ~ U[1.5, 4.5], rho ~ U[1.0, 2.5] per layer, 3 interface depths
+            uniform in (0, ny)), CFL 0.4 on the largest layer speed, 4
+            Gaussian pulses (sigma 8 cells) at uniform random positions.
+  smooth3d  3D elastic, order 2, 512^3 periodic, rho, lambda, mu each a smooth
+            periodic random field (16 Fourier modes, |k| <= 4) mapped to
+            [1, 3], CFL 0.3 on the largest P-wave speed, explosive Gaussian
+            (sigma 8 cells) on the three normal stresses.
+  shots     64 independent layered 2D shots, sides U{256..2048}, step counts
+            U{500..5000}.
+  requests  Poisson stream of mixed 2D layered / 3D smooth requests.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BASE_SEED = 20231001
+
+
+def seed_for(workload_id: int, instance: int = 0) -> int:
+    return BASE_SEED + 1000 * workload_id + instance
+
+
+# ------------------------------------------------------------ primitives --
+
+def periodic_offsets(n: int, centre: float) -> np.ndarray:
+    """Minimum-image offsets of grid indices 0..n-1 from `centre`."""
+    d = np.arange(n, dtype=np.float64) - centre
+    return d - n * np.round(d / n)
+
+
+def gaussian2d(nx, ny, cx, cy, sigma, amplitude=1.0):
+    dx = periodic_offsets(nx, cx)
+    dy = periodic_offsets(ny, cy)
+    r2 = dy[:, None] ** 2 + dx[None, :] ** 2
+    return amplitude * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def gaussian3d(nx, ny, nz, cx, cy, cz, sigma, amplitude=1.0):
+    dx = periodic_offsets(nx, cx)
+    dy = periodic_offsets(ny, cy)
+    dz = periodic_offsets(nz, cz)
+    r2 = dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2
+    return amplitude * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def layered_profile(ny, nlayers, rng, c_range=(1.5, 4.5), rho_range=(1.0, 2.5)):
+    """Per-row (depth) wave speed and density of a layered medium."""
+    depths = np.sort(rng.uniform(0.0, ny, size=nlayers - 1))
+    c_layer = rng.uniform(*c_range, size=nlayers)
+    rho_layer = rng.uniform(*rho_range, size=nlayers)
+    rows = np.arange(ny, dtype=np.float64)
+    layer = np.searchsorted(depths, rows, side="right")
+    return c_layer[layer], rho_layer[layer], c_layer
+
+
+def smooth_field3d(nx, ny, nz, rng, lo=1.0, hi=3.0, nmodes=16, kmax=4):
+    """Smooth periodic random field: a sum of nmodes random Fourier modes with
+    integer wave vectors |k| <= kmax, mapped affinely onto [lo, hi]."""
+    ks = []
+    while len(ks) < nmodes:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if 0 < np.dot(k, k) <= kmax * kmax:
+            ks.append(k)
+    x = np.arange(nx) / nx
+    y = np.arange(ny) / ny
+    z = np.arange(nz) / nz
+    f = np.zeros((nz, ny, nx))
+    for k in ks:
+        phase = rng.uniform(0, 2 * math.pi)
+        a = rng.normal()
+        ex = np.exp(2j * math.pi * k[0] * x)
+        ey = np.exp(2j * math.pi * k[1] * y)
+        ez = np.exp(2j * math.pi * k[2] * z)
+        f += a * np.real(np.exp(1j * phase) * ez[:, None, None] *
+                         ey[None, :, None] * ex[None, None, :])
+    fmin, fmax = f.min(), f.max()
+    if fmax == fmin:
+        return np.full_like(f, lo)
+    return lo + (hi - lo) * (f - fmin) / (fmax - fmin)
+
+
+# ------------------------------------------------------------- workloads --
+
+@dataclass
+class Acoustic2D:
+    nx: int
+    ny: int
+    order: int
+    dx: float
+    dt: float
+    rho: np.ndarray          # [ny, nx] at p points
+    kappa: np.ndarray        # [ny, nx] bulk modulus rho c^2 (= 1/beta)
+    p0: np.ndarray           # [ny, nx] initial pressure
+    vx0: np.ndarray | None = None
+    vy0: np.ndarray | None = None
+    nsteps: int = 0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+    def fields(self):
+        z = np.zeros((self.ny, self.nx))
+        return {"vx": z if self.vx0 is None else self.vx0,
+                "vy": z if self.vy0 is None else self.vy0, "p": self.p0}
+
+
+@dataclass
+class Elastic3D:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dt: float
+    rho: np.ndarray
+    lam: np.ndarray
+    mu: np.ndarray
+    init: dict               # field name -> [nz, ny, nx] array (missing = 0)
+    nsteps: int = 0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+    order: int = 2
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def fields(self):
+        names = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
+        z = np.zeros((self.nz, self.ny, self.nx))
+        return {k: self.init.get(k, z) for k in names}
+
+
+def small2d(n=128, nsteps=1000, order=2, cfl=0.5, sigma=8.0) -> Acoustic2D:
+    """Homogeneous rho = c = 1, dx = 1, centred Gaussian pressure pulse."""
+    dt = cfl * 1.0 / 1.0
+    ones = np.ones((n, n))
+    return Acoustic2D(n, n, order, 1.0, dt, ones, ones.copy(),
+                      gaussian2d(n, n, n // 2, n // 2, sigma), nsteps=nsteps,
+                      name=f"acoustic2d-o{order}-{n}x{n}-homogeneous")
+
+
+def layered2d(nx=4096, ny=None, nsteps=10000, order=4, cfl=0.4, nlayers=4,
+              npulses=4, sigma=8.0, seed=None) -> Acoustic2D:
+    ny = nx if ny is None else ny
+    rng = np.random.default_rng(seed_for(2) if seed is None else seed)
+    c_row, rho_row, c_layer = layered_profile(ny, nlayers, rng)
+    rho = np.repeat(rho_row[:, None], nx, axis=1)
+    kappa = np.repeat((rho_row * c_row ** 2)[:, None], nx, axis=1)
+    dx = 1.0
+    dt = cfl * dx / float(c_layer.max())
+    p0 = np.zeros((ny, nx))
+    for _ in range(npulses):
+        cx = rng.integers(0, nx)
+        cy = rng.integers(0, ny)
+        p0 += gaussian2d(nx, ny, cx, cy, sigma)
+    return Acoustic2D(nx, ny, order, dx, dt, rho, kappa, p0, nsteps=nsteps,
+                      name=f"acoustic2d-o{order}-{nx}x{ny}-layered",
+                      meta={"c_max": float(c_layer.max())})
+
+
+def smooth3d(n=512, nsteps=2000, cfl=0.3, sigma=8.0, seed=None,
+             nx=None, ny=None, nz=None) -> Elastic3D:
+    nx = n if nx is None else nx
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    rng = np.random.default_rng(seed_for(3) if seed is None else seed)
+    rho = smooth_field3d(nx, ny, nz, rng)
+    lam = smooth_field3d(nx, ny, nz, rng)
+    mu = smooth_field3d(nx, ny, nz, rng)
+    cp_max = float(np.sqrt((lam + 2 * mu) / rho).max())
+    dx = 1.0
+    dt = cfl * dx / cp_max
+    g = gaussian3d(nx, ny, nz, nx // 2, ny // 2, nz // 2, sigma)
+    init = {"sxx": g, "syy": g.copy(), "szz": g.copy()}
+    return Elastic3D(nx, ny, nz, dx, dt, rho, lam, mu, init, nsteps=nsteps,
+                     name=f"elastic3d-o2-{nx}x{ny}x{nz}-smooth",
+                     meta={"cp_max": cp_max})
+
+
+def shot_sizes(nshots=64, seed=None, side=(256, 2048), steps=(500, 5000)):
+    """(nx, ny, nsteps) of each shot of the batched workload."""
+    rng = np.random.default_rng(seed_for(4) if seed is None else seed)
+    out = []
+    for _ in range(nshots):
+        nx = int(rng.integers(side[0], side[1] + 1))
+        ny = int(rng.integers(side[0], side[1] + 1))
+        ns = int(rng.integers(steps[0], steps[1] + 1))
+        out.append((nx, ny, ns))
+    return out
+
+
+def shot(nx, ny, nsteps, index, order=4, cfl=0.4) -> Acoustic2D:
+    """One shot of the batched workload: its own layered medium and pulse."""
+    a = layered2d(nx, ny, nsteps=nsteps, order=order, cfl=cfl, npulses=1,
+                  seed=seed_for(4, 1 + index))
+    a.name = f"shot{index}-{nx}x{ny}"
+    return a
+
+
+@dataclass
+class Request:
+    arrival: float           # seconds after the stream starts
+    kind: str                # 'acoustic2d' or 'elastic3d'
+    size: int                # grid side
+    nsteps: int
+    precision: str           # 'f32' or 'f16+comp'
+    index: int
+
+
+def request_stream(nreq=500, rate=1.3, seed=None, frac2d=0.7,
+                   side2d=(512, 4096), side3d=(128, 384),
+                   steps=(1000, 10000)):
+    """Poisson arrivals of mixed 2D/3D requests, precision 50/50."""
+    rng = np.random.default_rng(seed_for(5) if seed is None else seed)
+    t = 0.0
+    out = []
+    for i in range(nreq):
+        t += rng.exponential(1.0 / rate)
+        if rng.uniform() < frac2d:
+            kind, size = "acoustic2d", int(rng.integers(side2d[0], side2d[1] + 1))
+        else:
+            kind, size = "elastic3d", int(rng.integers(side3d[0], side3d[1] + 1))
+        ns = int(rng.integers(steps[0], steps[1] + 1))
+        prec = "f32" if rng.uniform() < 0.5 else "f16+comp"
+        out.append(Request(t, kind, size, ns, prec, i))
+    return out
+
+
+def request_problem(req: Request):
+    """Concrete inputs of a request (own seed per request index)."""
+    if req.kind == "acoustic2d":
+        return layered2d(req.size, req.size, nsteps=req.nsteps, npulses=1,
+                         seed=seed_for(5, 1 + req.index))
+    return smooth3d(req.size, nsteps=req.nsteps, seed=seed_for(5, 1 + req.index))
