@@ -1,0 +1,228 @@
+"""Benchmark: grid-point updates per second of the 2D acoustic hot path.
+
+Workload (the paper's acoustic system at production size): 4096 x 4096
+periodic grid, 4th-order staggered stencil, 4-layer medium (c in [1.5, 4.5],
+rho in [1.0, 2.5]), CFL 0.4, four Gaussian pressure pulses, 10000 leapfrog
+steps by default; synthetic, seeded inputs.  A "step" is one full leapfrog
+step of the whole grid (both half-steps, every field, the solution update
+of Alg. 1 or Alg. 2); the discrete energy is computed in fp64 every 1000
+steps inside the timed region.
+
+The headline value is fp16 storage with the 6-operation compensated update
+(TwoSum); fp32, plain fp16 and plain bf16 run on the same workload for
+comparison.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "grid-point updates/s (FP16+comp vs FP32) at fixed energy drift; p50/p99 latency"
+ENERGY_EVERY = 1000
+
+# Algorithmic HBM bytes per cell and step of the fused acoustic kernel: every
+# field (vx, vy, p) and, with compensation, every compensation term read and
+# written once, the two fp32 material arrays (b, kappa) read once.
+def bytes_per_cell(storage: str, comp: str) -> int:
+    e = 4 if storage == "f32" else 2
+    fields = 3 * e * 2
+    comps = 3 * e * 2 if comp != "none" else 0
+    return fields + comps + 2 * 4
+
+
+VARIANTS = [("f16", "twosum"), ("f32", "none"), ("f16", "none"), ("bf16", "none")]
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("acoustic2d.hip", "hw_device.h", "hw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2310_00236_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_acoustic2d_4096_o4.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != kernel_source_digest():
+        return None
+    v = rec.get("variants", {}).get(tag)
+    return None if v is None else v.get("hbm_bytes_per_launch")
+
+
+def run_variant(hw, torch, w, storage, comp, steps, warmup, tile):
+    pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, w.order, storage, comp, w.dx,
+                    w.dt, 0, (warmup + steps) // ENERGY_EVERY + 4)
+    plan = hw.Plan(pb)
+    plan.set_tile(tile)
+    plan.set_material([w.rho, w.kappa])
+    plan.set_fields(w.fields())
+    stream = torch.cuda.current_stream()
+    plan.record_energy()
+    plan.advance(warmup, ENERGY_EVERY)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    plan.advance(steps, ENERGY_EVERY)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    # average duration of the step kernel alone: back-to-back launches with
+    # no energy evaluation in between, bracketed by events on the same stream
+    nk = min(200, max(steps, 1))
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record(stream)
+    plan.advance(nk, 0)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kernel_ms = k0.elapsed_time(k1) / nk
+    energy, esteps = plan.energy_trace()
+    plan.close()
+    drift = float(np.max(np.abs(energy - energy[0])) / energy[0])
+    cells = w.nx * w.ny
+    return {
+        "glups": cells * steps / (ms * 1e-3) / 1e9,
+        "ms_per_step": ms / steps,
+        "wall_s": wall,
+        "kernel_ms": kernel_ms,
+        "energy_drift": drift,
+        "energy_samples": int(len(energy)),
+        "bytes_per_cell": bytes_per_cell(storage, comp),
+        "hbm_gbs_algorithmic": bytes_per_cell(storage, comp) * cells / (kernel_ms * 1e-3) / 1e9,
+    }
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The oracle (fp16 storage, fp32 stencil, TwoSum update, i.e. the same
+    arithmetic as the headline variant) on the same 4096^2 workload, from its
+    initial state, for as many whole steps as fit in about target_s."""
+    import oracle
+    f = {k: oracle.round_to(v, "f16") for k, v in w.fields().items()}
+    args = (w.nx, w.ny, w.order, w.dx, w.dt, w.rho, w.kappa)
+    t = time.perf_counter()
+    f, c, _ = oracle.acoustic2d(*args, f, storage="f16", stencil="f32",
+                                comp="twosum", nsteps=1)
+    t1 = time.perf_counter() - t
+    more = max(0, int(target_s / t1) - 1)
+    t = time.perf_counter()
+    if more:
+        oracle.acoustic2d(*args, f, storage="f16", stencil="f32", comp="twosum",
+                          comps=c, nsteps=more)
+    tm = time.perf_counter() - t
+    steps = 1 + more
+    secs = t1 + tm
+    return {"value": w.nx * w.ny * steps / secs / 1e9, "unit": "GLUPS",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{steps} steps of the {w.nx}x{w.ny} order-4 layered "
+                      f"workload, fp16+TwoSum emulated, {secs:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=4096, help="grid side")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="tile shape index (-1: best from the tuning table)")
+    ap.add_argument("--variants", default="all",
+                    help="comma list of storage+comp, e.g. f16+twosum,f32+none")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2310_00236_amd as hw
+    import workloads
+    from paper_2310_00236_amd import tuning
+
+    torch.cuda.init()
+    w = workloads.layered2d(args.n, nsteps=args.steps)
+    variants = VARIANTS if args.variants == "all" else \
+        [tuple(v.split("+")) for v in args.variants.split(",")]
+    results = {}
+    tiles = {}
+    for storage, comp in variants:
+        tile = args.tile if args.tile >= 0 else tuning.best_tile(
+            "acoustic2d", w.order, storage, comp, w.nx, w.ny)
+        tiles[f"{storage}+{comp}"] = tile
+        results[f"{storage}+{comp}"] = run_variant(hw, torch, w, storage, comp,
+                                                   args.steps, args.warmup, tile)
+        print(f"# {storage}+{comp}: {results[f'{storage}+{comp}']}", file=sys.stderr,
+              flush=True)
+    head_key = "f16+twosum" if "f16+twosum" in results else next(iter(results))
+    head = results[head_key]
+    cells = w.nx * w.ny
+    traffic = measured_traffic(head_key)
+    roofline = {
+        "bound": "hbm",
+        "achieved": head["hbm_gbs_algorithmic"],
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": head["hbm_gbs_algorithmic"] / PEAK_HBM_GBS,
+        "traffic": traffic,
+        "kernel": "ac2d_step_kernel",
+        "bytes_per_cell_step": head["bytes_per_cell"],
+        "cells_per_launch": cells,
+        "kernel_ms": head["kernel_ms"],
+    }
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    f32 = results.get("f32+none")
+    out = {
+        "metric": METRIC,
+        "value": head["glups"],
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16" if head_key.startswith("f16") else head_key.split("+")[0],
+        "data": "synthetic",
+        "config": {"workload": f"acoustic2d order-4 {w.nx}x{w.ny} periodic, "
+                               f"4-layer medium, CFL 0.4, 4 Gaussian pulses, "
+                               f"{args.steps} steps",
+                   "variant": head_key, "tile": list(hw.tiles("acoustic2d")[tiles[head_key]]),
+                   "energy_every": ENERGY_EVERY},
+        "energy_drift": head["energy_drift"],
+        "vs_f32": (head["glups"] / f32["glups"]) if f32 else None,
+        "variants": {k: {"glups": v["glups"], "energy_drift": v["energy_drift"],
+                         "kernel_ms": v["kernel_ms"],
+                         "hbm_gbs_algorithmic": v["hbm_gbs_algorithmic"],
+                         "frac_hbm": v["hbm_gbs_algorithmic"] / PEAK_HBM_GBS,
+                         "tile": list(hw.tiles("acoustic2d")[tiles[k]])}
+                     for k, v in results.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * halfwave.h -- C ABI of the MI355X (gfx950) library for staggered-grid
+ * leapfrog wave propagation with half-precision state and compensated
+ * updates (Gao & Harms, "Half precision wave simulation").
+ *
+ * The library computes, on one GPU:
+ *   - the 2D acoustic system of Eq. (1) (Sec. 3): rho dvx/dt = dp/dx,
+ *     rho dvy/dt = dp/dy, beta dp/dt = dvx/dx + dvy/dy, with the signs as
+ *     printed; staggered grid, 2nd- or 4th-order staggered stencil (the 4th
+ *     order one has coefficients [1/24, -9/8, 9/8, -1/24], Sec. 3), periodic
+ *     in both directions, 2nd-order staggered leapfrog in time;
+ *   - the 3D velocity-stress elastic system, the 3D form of Eq. (A1)
+ *     (App. A), 2nd order, on the standard staggered layout, periodic;
+ *   - per step and per field, the update of Alg. 1 (plain, V += R) or of
+ *     Alg. 2 (compensated, Sec. 4) with the 3-operation sum (Code 1) or the
+ *     6-operation sum (Code 2), the fields and compensation terms held in
+ *     fp32, fp16 or bf16;
+ *   - the discrete energy of the scheme, in fp64 (Sec. 3 uses it as the
+ *     diagnosis tool; its formula is given at hw_record_energy).
+ *
+ * Grid and layout.  2D arrays are row-major [ny][nx] (x fastest); p[j][i] is
+ * at (i dx, j dx), vx[j][i] at ((i+1/2) dx, j dx), vy[j][i] at
+ * (i dx, (j+1/2) dx).  3D arrays are [nz][ny][nx]; normal stresses and the
+ * material at (i, j, k), vx at (i+1/2, j, k), vy at (i, j+1/2, k), vz at
+ * (i, j, k+1/2), sxy at (i+1/2, j+1/2, k), sxz at (i+1/2, j, k+1/2), syz at
+ * (i, j+1/2, k+1/2).  All indices wrap periodically.  The state at the top of
+ * a step is (v^{n-1/2}, p^n) (or sigma^n): velocities are updated first.
+ *
+ * Field order:     acoustic  {vx, vy, p}
+ *                  elastic   {vx, vy, vz, sxx, syy, szz, sxy, sxz, syz}
+ * Material order:  acoustic  {rho, kappa} at p points, kappa = 1/beta
+ *                  elastic   {rho, lambda, mu} at cell centres
+ * The material is used as fp32 values b = fp32(1/rho), kappa, lambda, mu;
+ * staggered buoyancy is the mean of the two adjacent b, the shear modulus on
+ * an edge the mean of the four adjacent mu.  dt and dx enter through the
+ * stencil weights w_k = fp32(c_k * (dt/dx)).
+ *
+ * Memory.  The library allocates no device memory.  The caller provides one
+ * device buffer (the arena) per plan, at least hw_footprint() bytes, 256-byte
+ * aligned, which must outlive the plan; the plan carves fields, compensation
+ * terms, material, energy trace and a staging area out of it.  Host arrays
+ * passed to the library are read or written during the call or, for the
+ * *_async-style calls on a stream, until that stream has been synchronised.
+ * Streams are hipStream_t handles passed as void* (NULL = the null stream).
+ *
+ * Errors.  Every call returns an hw_status; on failure nothing observable has
+ * changed unless stated, and hw_last_error() returns a message for the
+ * calling thread.  No call throws or aborts.
+ */
+#ifndef HALFWAVE_H
+#define HALFWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HW_ABI_VERSION 1u
+
+typedef enum hw_status {
+    HW_OK = 0,
+    HW_E_INVAL = 1,      /* bad argument, size or enum                       */
+    HW_E_UNSTABLE = 2,   /* Courant number at or above the stability bound   */
+    HW_E_RANGE = 3,      /* a value does not fit the storage format          */
+    HW_E_NOMEM = 4,      /* arena or energy trace too small                  */
+    HW_E_DEVICE = 5,     /* a HIP call failed                                */
+    HW_E_NONFINITE = 6,  /* the state became inf/NaN (sticky, see below)     */
+    HW_E_STATE = 7       /* call out of order (e.g. advance before upload)   */
+} hw_status;
+
+enum hw_physics { HW_ACOUSTIC2D = 0, HW_ELASTIC3D = 1 };
+enum hw_storage { HW_F32 = 0, HW_F16 = 1, HW_BF16 = 2 };
+enum hw_comp { HW_COMP_NONE = 0, HW_COMP_FAST2SUM = 1, HW_COMP_TWOSUM = 2 };
+
+typedef struct hw_problem {
+    uint32_t abi_version;  /* must be HW_ABI_VERSION                          */
+    int32_t physics;       /* enum hw_physics                                 */
+    int32_t order;         /* spatial order: 2 or 4 (acoustic), 2 (elastic)   */
+    int32_t storage;       /* enum hw_storage: format of fields and comps     */
+    int32_t comp;          /* enum hw_comp: update of Alg. 1 or Alg. 2        */
+    int32_t scale_log2;    /* fields are held multiplied by 2^scale_log2, to
+                              keep them inside the storage range (Sec. 5);
+                              results are returned unscaled. |.| <= 60       */
+    int64_t nx, ny, nz;    /* cells per axis, >= 1; nz must be 1 for 2D       */
+    double dx;             /* grid spacing, all axes, > 0                     */
+    double dt;             /* time step, > 0                                  */
+    int64_t trace_cap;     /* energy samples reserved in the arena, >= 0      */
+} hw_problem;
+
+typedef struct hw_plan hw_plan;
+
+/* Version of the ABI the library implements (HW_ABI_VERSION). */
+uint32_t hw_abi_version(void);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *hw_last_error(void);
+
+/* Number of fields (3 acoustic, 9 elastic) and material arrays (2, 3). */
+int32_t hw_num_fields(int32_t physics);
+int32_t hw_num_materials(int32_t physics);
+
+/* Device bytes a plan for *pb needs.  Host only; works without a GPU.
+ * HW_E_INVAL for an invalid problem. */
+hw_status hw_footprint(const hw_problem *pb, size_t *device_bytes);
+
+/* Stability bound on the Courant number c_eff*dt/dx for this physics and
+ * order: 1/sqrt(2) (2D, order 2), 1/(sqrt(2)*(9/8+1/24)) (2D, order 4),
+ * 1/sqrt(3) (3D).  Returns a negative value for invalid arguments. */
+double hw_cfl_bound(int32_t physics, int32_t order);
+
+/* Create a plan: validate *pb and carve the arena.  Host only, no HIP call.
+ * arena: device pointer, 256-byte aligned, arena_bytes >= hw_footprint().
+ * *out is written only on success; the plan borrows the arena. */
+hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
+                         hw_plan **out);
+
+/* Destroy a plan (releases host-side objects only; never frees the arena).
+ * Waits for nothing: the caller must not destroy a plan with work in flight. */
+void hw_plan_destroy(hw_plan *plan);
+
+/* Upload the material: hw_num_materials() host fp64 arrays, in the material
+ * order above, each of nx*ny*nz values.  Validates on the host first: all
+ * values finite, rho > 0, kappa > 0 (acoustic), mu > 0 and
+ * 3 lambda + 2 mu > 0 (elastic), the fp32 values finite, and the Courant
+ * number below hw_cfl_bound() (HW_E_INVAL / HW_E_UNSTABLE).  The Courant
+ * number uses, for every cell face, the staggered buoyancy of the face times
+ * the larger modulus (kappa, or lambda + 2 mu) of the two cells it joins.
+ * Then copies and converts on `stream`. */
+hw_status hw_set_material(hw_plan *plan, const double *const *material,
+                          void *stream);
+
+/* Upload the initial state: hw_num_fields() host fp64 arrays in the field
+ * order above (a NULL entry means all zeros).  Each value times
+ * 2^scale_log2 must be finite and within the storage format's largest
+ * finite value (HW_E_RANGE); it is rounded to nearest-even.  Compensation
+ * terms, step counter and energy trace are reset.  Async on `stream`. */
+hw_status hw_set_fields(hw_plan *plan, const double *const *fields,
+                        void *stream);
+
+/* Advance nsteps >= 0 leapfrog steps (Alg. 1 or 2 per the plan).  If
+ * energy_every > 0, the energy is appended to the trace for every state
+ * whose step count is a multiple of energy_every (including the starting
+ * state, unless already recorded).  HW_E_NOMEM if the trace would overflow
+ * (nothing is launched then).  Async on `stream`. */
+hw_status hw_advance(hw_plan *plan, int64_t nsteps, int64_t energy_every,
+                     void *stream);
+
+/* Append the energy of the current state to the trace.  Async.  The energy
+ * (fp64, of the stored state (v^{n-1/2}, p^n)):
+ *   acoustic  E = dx^2/2 * sum[ p^2/kappa + vx^- vx^+ / bx + vy^- vy^+ / by ]
+ *   elastic   E = dx^3/2 * sum[ v^- . v^+ / b + s_n^T C^-1 s_n + s_ij^2/mu_ij ]
+ * where v^+ = v^- + b * (stencil of p or div sigma) is recomputed in fp64,
+ * C = lambda 1 1^T + 2 mu I acts on the normal stresses.  A non-finite
+ * energy sets the plan's sticky HW_E_NONFINITE, reported by hw_energy_trace
+ * and hw_get_fields. */
+hw_status hw_record_energy(hw_plan *plan, void *stream);
+
+/* Copy the energy trace to the host: energy[k] and step[k] (either may be
+ * NULL) for k < min(cap, count); *n_out = count.  Synchronises `stream`. */
+hw_status hw_energy_trace(hw_plan *plan, double *energy, int64_t *step,
+                          int64_t cap, int64_t *n_out, void *stream);
+
+/* Copy the state to the host as fp64 (exact widening, unscaled): fields and,
+ * if comps is non-NULL, the compensation terms (zeros for HW_COMP_NONE),
+ * both in the field order.  NULL entries are skipped.  Synchronises. */
+hw_status hw_get_fields(hw_plan *plan, double *const *fields,
+                        double *const *comps, void *stream);
+
+/* Current step count of the plan. */
+int64_t hw_plan_step(const hw_plan *plan);
+
+/* Checkpoint: the state (fields, compensation terms, step count) as an
+ * opaque byte blob; importing it into a plan of the same problem and
+ * continuing gives bit-identical results to never having stopped.  The
+ * energy trace is not part of the blob.  Both synchronise `stream`. */
+hw_status hw_state_size(const hw_plan *plan, size_t *bytes);
+hw_status hw_state_export(hw_plan *plan, void *blob, size_t bytes,
+                          void *stream);
+hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
+                          void *stream);
+
+/* Kernel tile shapes (x by y cells per workgroup) the library was built
+ * with.  hw_plan_set_tile picks one for a plan; every tile shape gives
+ * bit-identical results. */
+int32_t hw_tile_count(int32_t physics);
+hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx,
+                       int32_t *ty);
+hw_status hw_plan_set_tile(hw_plan *plan, int32_t tile);
+
+/* Advance n plans (0 < n) by nsteps[i] steps each, batching all plans with
+ * the same physics, order, storage and compensation into one launch per
+ * time step that covers every tile of every such plan still running.  Each
+ * plan's results (fields, comps, energy trace) are bit-identical to
+ * hw_advance(plan, nsteps[i], energy_every) on it alone.  Plans are
+ * borrowed and must be distinct.  tile >= 0 selects the batched kernel's
+ * tile shape (as hw_tile_info), -1 uses the first plan's.  Async. */
+hw_status hw_batch_advance(hw_plan *const *plans, int32_t n,
+                           const int64_t *nsteps, int64_t energy_every,
+                           int32_t tile, void *stream);
+
+/* Blocking convenience: create a plan in the arena, upload material and
+ * fields, advance nsteps with the energy every energy_every steps, download
+ * the fields into the same arrays (fields must be non-NULL host arrays) and
+ * copy up to energy_cap energies.  *n_energy receives the trace length. */
+hw_status hw_simulate(const hw_problem *pb, const double *const *material,
+                      double *const *fields, int64_t nsteps,
+                      int64_t energy_every, double *energy, int64_t energy_cap,
+                      int64_t *n_energy, void *arena, size_t arena_bytes,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HALFWAVE_H */

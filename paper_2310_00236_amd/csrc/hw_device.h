@@ -1,0 +1,129 @@
+// Device-side numeric primitives: storage formats, round-to-nearest-even
+// conversions and the solution updates of Alg. 1 and Alg. 2 (Sec. 4).
+//
+// Values of a storage format are carried in fp32 registers (every fp16 and
+// bf16 value is exactly an fp32 value).  An operation of the storage format
+// is an fp32 operation followed by rounding to the format: for operands with
+// p <= 11 significand bits the fp32 result (24 bits >= 2p + 2) rounded once
+// more equals the correctly rounded p-bit result, so this is IEEE fp16/bf16
+// arithmetic.  The whole library is compiled without floating-point
+// contraction, so every a*b+c below is two rounded operations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace hw {
+
+enum Comp { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2 };
+
+// ---------------------------------------------------------------- formats
+
+struct F32 {
+    using store_t = float;
+    static constexpr int id = 0;
+    __device__ __forceinline__ static float load(store_t x) { return x; }
+    __device__ __forceinline__ static store_t store(float x) { return x; }
+    __device__ __forceinline__ static float rn(float x) { return x; }
+};
+
+// Opaque copy of an fp32 value: the compiler may not fold the operation
+// that produced it into the consumer.  Without it the backend merges
+// "fp32 multiply, then convert to fp16" into one mixed-precision fma that
+// rounds the exact product once (and turns a -0 product into +0), which is
+// a different operation from the two roundings the method defines.
+__device__ __forceinline__ float opaque(float x)
+{
+    __asm__("" : "+v"(x));
+    return x;
+}
+
+struct F16 {
+    using store_t = _Float16;
+    static constexpr int id = 1;
+    __device__ __forceinline__ static float load(store_t x) { return (float)x; }
+    // fp32 -> fp16 conversion rounds to nearest even, keeps subnormals and
+    // overflows to infinity.
+    __device__ __forceinline__ static store_t store(float x)
+    {
+        return (_Float16)opaque(x);
+    }
+    __device__ __forceinline__ static float rn(float x)
+    {
+        return (float)(_Float16)opaque(x);
+    }
+};
+
+struct BF16 {
+    using store_t = uint16_t;
+    static constexpr int id = 2;
+    __device__ __forceinline__ static float load(store_t x) {
+        return __uint_as_float((uint32_t)x << 16);
+    }
+    // Round-to-nearest-even on the bit pattern: add 0x7fff plus the lowest
+    // kept bit, keep the top 16 bits.  Carries propagate into the exponent,
+    // so values past the largest finite bf16 become infinity; NaNs are kept
+    // quiet.
+    __device__ __forceinline__ static store_t store(float x) {
+        uint32_t u = __float_as_uint(x);
+        if ((u & 0x7fffffffu) > 0x7f800000u)
+            return (store_t)((u >> 16) | 0x40u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (store_t)(u >> 16);
+    }
+    __device__ __forceinline__ static float rn(float x) { return load(store(x)); }
+};
+
+template <int ID> struct FormatOf;
+template <> struct FormatOf<0> { using type = F32; };
+template <> struct FormatOf<1> { using type = F16; };
+template <> struct FormatOf<2> { using type = BF16; };
+
+// ------------------------------------------------------- solution updates
+
+// v and c hold values of format S.  inc is the fp32 increment R of the
+// paper's algorithms after scaling by the material.
+//   plain (Alg. 1):     v <- v (+) RN(inc)
+//   compensated (Alg. 2, compensation added after scaling):
+//                       y = RN(inc + c);  (v, c) <- sum(v, y)
+// with sum the 3-operation form (Code 1) or the 6-operation form (Code 2).
+template <class S, int COMP>
+__device__ __forceinline__ void update(float &v, float &c, float inc)
+{
+    if constexpr (COMP == COMP_NONE) {
+        float r = S::rn(inc);
+        v = S::rn(v + r);
+    } else {
+        float y = S::rn(inc + c);
+        float s = S::rn(v + y);
+        if constexpr (COMP == COMP_FAST2SUM) {
+            float z = S::rn(s - v);
+            c = S::rn(y - z);
+        } else {
+            float pa = S::rn(s - y);
+            float pb = S::rn(s - pa);
+            float da = S::rn(v - pa);
+            float db = S::rn(y - pb);
+            c = S::rn(da + db);
+        }
+        v = s;
+    }
+}
+
+// Periodic index for offsets of at most one period beyond [0, n).
+__device__ __forceinline__ int64_t wrap1(int64_t i, int64_t n)
+{
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// Periodic index for any offset (tiny grids where a halo spans several
+// periods).
+__device__ __forceinline__ int64_t wrapn(int64_t i, int64_t n)
+{
+    int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace hw

@@ -1,0 +1,93 @@
+// Internal structures shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "halfwave.h"
+
+namespace hw {
+
+constexpr int kMaxBatch = 64;     // shots per batched launch
+constexpr int kThreads = 256;     // threads per workgroup (4 wavefronts)
+constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
+
+// Device-resident description of one 2D acoustic plan.  Buffers are
+// row-major with a padded row pitch (elements).  The velocity fields and
+// their compensation terms ping-pong between two sets so that a tile can
+// recompute its neighbours' new velocities from old values; the pressure
+// compensation is read and written only by the cell's owner and stays in
+// place.
+struct Ac2dDesc {
+    int64_t nx, ny, pitch;
+    float w1, w2;                 // stencil weights c_k * dt/dx (fp32)
+    const float *b;               // 1/rho at p points
+    const float *k;               // kappa at p points
+    void *vx[2], *vy[2], *p[2];   // field sets (storage format)
+    void *cvx[2], *cvy[2];        // velocity compensation sets
+    void *cp;                     // pressure compensation (in place)
+};
+
+// Device-resident description of one 3D elastic plan (updated in place by
+// a velocity pass followed by a stress pass).
+struct El3dDesc {
+    int64_t nx, ny, nz, pitch, slab;
+    float w;                      // dt/dx (fp32)
+    const float *b, *lam, *mu;    // at cell centres
+    void *f[9];                   // vx vy vz sxx syy szz sxy sxz syz
+    void *c[9];                   // compensation terms (nullptr if none)
+};
+
+// Arguments of one batched launch: the shots it covers, the parity (which
+// field set is current) of each, the first global tile of each shot and
+// its tile counts along x and y (for the launch's tile shape; 3D shots have
+// tiles_x * tiles_y tiles per z slice).
+template <class Desc>
+struct BatchArgs {
+    int32_t nshots;
+    int32_t total_tiles;
+    int32_t parity[kMaxBatch];
+    int32_t tiles_x[kMaxBatch];
+    int32_t tiles_y[kMaxBatch];
+    int32_t tile_start[kMaxBatch + 1];
+    const Desc *desc[kMaxBatch];
+};
+
+using Ac2dBatch = BatchArgs<Ac2dDesc>;
+using El3dBatch = BatchArgs<El3dDesc>;
+
+struct TileShape { int tx, ty; };
+
+// Tile shapes compiled into the library (x by y cells per workgroup).
+constexpr TileShape kTiles2D[] = {{64, 16}, {128, 8}, {256, 4}, {64, 8}, {128, 16}};
+constexpr TileShape kTiles3D[] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}};
+constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
+constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
+
+// Launchers (one translation unit per physics).
+hipError_t launch_ac2d_step(const Ac2dBatch &a, int storage, int comp,
+                            int order, int tile, hipStream_t s);
+hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
+                              int64_t ny, int storage, int order,
+                              double *partial, hipStream_t s);
+hipError_t launch_el3d_step(const El3dBatch &a, int storage, int comp,
+                            int tile, hipStream_t s);
+hipError_t launch_el3d_energy(const El3dDesc *d_desc, int64_t rows,
+                              int storage, double *partial, hipStream_t s);
+hipError_t launch_energy_finish(const double *partial, int64_t n,
+                                double factor, double *out, int32_t *flag,
+                                hipStream_t s);
+
+// Conversions between fp64 host-layout arrays and the device layouts.
+hipError_t launch_to_storage(const double *src, void *dst, int storage,
+                             int64_t nx, int64_t rows, int64_t pitch,
+                             double scale, hipStream_t s);
+hipError_t launch_from_storage(const void *src, double *dst, int storage,
+                               int64_t nx, int64_t rows, int64_t pitch,
+                               double scale, hipStream_t s);
+hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s);
+hipError_t launch_material(const double *src, float *dst, int reciprocal,
+                           int64_t nx, int64_t rows, int64_t pitch,
+                           hipStream_t s);
+
+}  // namespace hw

@@ -1,0 +1,872 @@
+// Host runtime behind the C ABI of halfwave.h: problem validation, arena
+// carving, uploads and downloads, the time loop, the energy trace,
+// checkpoints and batched launches over many plans.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "halfwave.h"
+#include "hw_internal.h"
+
+using namespace hw;
+
+namespace {
+
+thread_local std::string g_error;
+
+hw_status fail(hw_status st, const std::string &msg)
+{
+    g_error = msg;
+    return st;
+}
+
+#define HW_HIP(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return fail(HW_E_DEVICE, std::string(#call ": ") +                \
+                                         hipGetErrorString(e_));              \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kPitchAlign = 64;   // elements
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int esize(int storage) { return storage == HW_F32 ? 4 : 2; }
+
+double max_finite(int storage)
+{
+    switch (storage) {
+    case HW_F16: return 65504.0;
+    case HW_BF16: return 0x1.fep127;
+    default: return 0x1.fffffep127;
+    }
+}
+
+double cfl_bound(int physics, int order)
+{
+    if (physics == HW_ACOUSTIC2D) {
+        if (order == 2)
+            return 1.0 / std::sqrt(2.0);
+        if (order == 4)
+            return 1.0 / (std::sqrt(2.0) * (9.0 / 8.0 + 1.0 / 24.0));
+        return -1.0;
+    }
+    if (physics == HW_ELASTIC3D && order == 2)
+        return 1.0 / std::sqrt(3.0);
+    return -1.0;
+}
+
+// Layout of a plan inside its arena.
+struct Layout {
+    int nf = 0, nm = 0, sets = 1;
+    int64_t pitch = 0, slab = 0, rows = 0, cells = 0;
+    size_t field_bytes = 0, mat_bytes = 0;
+    size_t off_fld[2][9] = {}, off_cmp[2][9] = {};
+    size_t off_mat[3] = {}, off_staging = 0, off_partial = 0, off_trace = 0;
+    size_t off_flags = 0, off_desc = 0, total = 0;
+};
+
+hw_status validate(const hw_problem *pb)
+{
+    if (!pb)
+        return fail(HW_E_INVAL, "problem is NULL");
+    if (pb->abi_version != HW_ABI_VERSION)
+        return fail(HW_E_INVAL, "abi_version mismatch");
+    if (pb->physics != HW_ACOUSTIC2D && pb->physics != HW_ELASTIC3D)
+        return fail(HW_E_INVAL, "unknown physics");
+    if (cfl_bound(pb->physics, pb->order) < 0)
+        return fail(HW_E_INVAL, "unsupported order for this physics");
+    if (pb->storage < HW_F32 || pb->storage > HW_BF16)
+        return fail(HW_E_INVAL, "unknown storage format");
+    if (pb->comp < HW_COMP_NONE || pb->comp > HW_COMP_TWOSUM)
+        return fail(HW_E_INVAL, "unknown compensation mode");
+    if (pb->scale_log2 < -60 || pb->scale_log2 > 60)
+        return fail(HW_E_INVAL, "scale_log2 out of [-60, 60]");
+    if (pb->nx < 1 || pb->ny < 1 || pb->nz < 1)
+        return fail(HW_E_INVAL, "grid sizes must be >= 1");
+    if (pb->physics == HW_ACOUSTIC2D && pb->nz != 1)
+        return fail(HW_E_INVAL, "nz must be 1 for acoustic2d");
+    const double lim = 1u << 30;
+    if ((double)pb->nx > lim || (double)pb->ny > lim || (double)pb->nz > lim ||
+        (double)pb->nx * pb->ny * pb->nz > 0x1p40)
+        return fail(HW_E_INVAL, "grid too large");
+    if (!(pb->dx > 0) || !std::isfinite(pb->dx) || !(pb->dt > 0) ||
+        !std::isfinite(pb->dt))
+        return fail(HW_E_INVAL, "dx and dt must be finite and > 0");
+    if (pb->trace_cap < 0)
+        return fail(HW_E_INVAL, "trace_cap must be >= 0");
+    const float w = (float)(pb->dt / pb->dx);
+    if (!std::isfinite(w) || w == 0.0f)
+        return fail(HW_E_INVAL, "dt/dx does not fit fp32");
+    // tile counts must fit the 32-bit launch indexing
+    const double tiles = std::ceil(pb->nx / 32.0) * std::ceil(pb->ny / 1.0) * pb->nz;
+    if (tiles > 2.0e9)
+        return fail(HW_E_INVAL, "grid too large for one launch");
+    return HW_OK;
+}
+
+Layout make_layout(const hw_problem *pb)
+{
+    Layout L;
+    const bool ac = pb->physics == HW_ACOUSTIC2D;
+    L.nf = ac ? 3 : 9;
+    L.nm = ac ? 2 : 3;
+    L.sets = ac ? 2 : 1;
+    L.pitch = (pb->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+    L.slab = L.pitch * pb->ny;
+    L.rows = pb->ny * pb->nz;
+    L.cells = pb->nx * pb->ny * pb->nz;
+    L.field_bytes = align_up((size_t)(L.slab * pb->nz) * esize(pb->storage), kAlign);
+    L.mat_bytes = align_up((size_t)(L.slab * pb->nz) * 4, kAlign);
+    size_t off = 0;
+    for (int s = 0; s < L.sets; ++s)
+        for (int f = 0; f < L.nf; ++f) {
+            L.off_fld[s][f] = off;
+            off += L.field_bytes;
+        }
+    if (pb->comp != HW_COMP_NONE) {
+        for (int s = 0; s < L.sets; ++s)
+            for (int f = 0; f < L.nf; ++f) {
+                // the 2D pressure compensation is not ping-ponged
+                if (ac && f == 2 && s == 1) {
+                    L.off_cmp[s][f] = L.off_cmp[0][f];
+                    continue;
+                }
+                L.off_cmp[s][f] = off;
+                off += L.field_bytes;
+            }
+    }
+    for (int m = 0; m < L.nm; ++m) {
+        L.off_mat[m] = off;
+        off += L.mat_bytes;
+    }
+    L.off_staging = off;
+    off += align_up((size_t)L.cells * 8, kAlign);
+    L.off_partial = off;
+    off += align_up((size_t)L.rows * 8, kAlign);
+    L.off_trace = off;
+    off += align_up((size_t)std::max<int64_t>(pb->trace_cap, 1) * 8, kAlign);
+    L.off_flags = off;
+    off += kAlign;
+    L.off_desc = off;
+    off += align_up(std::max(sizeof(Ac2dDesc), sizeof(El3dDesc)), kAlign);
+    L.total = off;
+    return L;
+}
+
+struct KernelKey {
+    int physics, order, storage, comp;
+    bool operator<(const KernelKey &o) const
+    {
+        return std::tie(physics, order, storage, comp) <
+               std::tie(o.physics, o.order, o.storage, o.comp);
+    }
+};
+
+}  // namespace
+
+struct hw_plan {
+    hw_problem pb;
+    Layout L;
+    char *arena;
+    void *fld[2][9];
+    void *cmp[2][9];
+    float *mat[3];
+    double *staging, *partial, *trace;
+    int32_t *flags;
+    void *d_desc;
+    Ac2dDesc h2;
+    El3dDesc h3;
+    int cur = 0;
+    int64_t step = 0;
+    int64_t trace_n = 0;
+    int64_t last_logged = -1;
+    std::vector<int64_t> trace_steps;
+    bool have_material = false, have_fields = false;
+    int tile = 0;
+    double scale_up = 1.0, scale_down = 1.0;
+    KernelKey key() const { return {pb.physics, pb.order, pb.storage, pb.comp}; }
+};
+
+namespace {
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+int num_tiles(const hw_problem &pb) { return pb.physics == HW_ACOUSTIC2D ? kNumTiles2D : kNumTiles3D; }
+
+void tile_counts(const hw_plan *p, int tile, int32_t *tx, int32_t *ty, int32_t *total)
+{
+    const TileShape t = p->pb.physics == HW_ACOUSTIC2D ? kTiles2D[tile] : kTiles3D[tile];
+    *tx = (int32_t)((p->pb.nx + t.tx - 1) / t.tx);
+    *ty = (int32_t)((p->pb.ny + t.ty - 1) / t.ty);
+    *total = *tx * *ty * (int32_t)p->pb.nz;
+}
+
+// One time step for a group of plans sharing a kernel, in launches of at
+// most kMaxBatch shots.
+hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s)
+{
+    const hw_plan *p0 = plans[0];
+    for (int base = 0; base < n; base += kMaxBatch) {
+        const int m = std::min(kMaxBatch, n - base);
+        hipError_t e;
+        if (p0->pb.physics == HW_ACOUSTIC2D) {
+            Ac2dBatch a;
+            std::memset(&a, 0, sizeof(a));
+            a.nshots = m;
+            int64_t total = 0;
+            for (int i = 0; i < m; ++i) {
+                hw_plan *p = plans[base + i];
+                int32_t tx, ty, tt;
+                tile_counts(p, tile, &tx, &ty, &tt);
+                a.tile_start[i] = (int32_t)total;
+                a.tiles_x[i] = tx;
+                a.tiles_y[i] = ty;
+                a.parity[i] = p->cur;
+                a.desc[i] = (const Ac2dDesc *)p->d_desc;
+                total += tt;
+            }
+            if (total > INT32_MAX)
+                return fail(HW_E_INVAL, "batch has too many tiles for one launch");
+            a.tile_start[m] = (int32_t)total;
+            a.total_tiles = (int32_t)total;
+            e = launch_ac2d_step(a, p0->pb.storage, p0->pb.comp, p0->pb.order, tile, s);
+        } else {
+            El3dBatch a;
+            std::memset(&a, 0, sizeof(a));
+            a.nshots = m;
+            int64_t total = 0;
+            for (int i = 0; i < m; ++i) {
+                hw_plan *p = plans[base + i];
+                int32_t tx, ty, tt;
+                tile_counts(p, tile, &tx, &ty, &tt);
+                a.tile_start[i] = (int32_t)total;
+                a.tiles_x[i] = tx;
+                a.tiles_y[i] = ty;
+                a.desc[i] = (const El3dDesc *)p->d_desc;
+                total += tt;
+            }
+            if (total > INT32_MAX)
+                return fail(HW_E_INVAL, "batch has too many tiles for one launch");
+            a.tile_start[m] = (int32_t)total;
+            a.total_tiles = (int32_t)total;
+            e = launch_el3d_step(a, p0->pb.storage, p0->pb.comp, tile, s);
+        }
+        if (e != hipSuccess)
+            return fail(HW_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    }
+    for (int i = 0; i < n; ++i) {
+        hw_plan *p = plans[i];
+        if (p->pb.physics == HW_ACOUSTIC2D)
+            p->cur ^= 1;
+        p->step += 1;
+    }
+    return HW_OK;
+}
+
+hw_status record_energy(hw_plan *p, hipStream_t s)
+{
+    if (p->trace_n >= p->pb.trace_cap)
+        return fail(HW_E_NOMEM, "energy trace is full");
+    hipError_t e;
+    double factor = 0.5 * p->pb.dx * p->pb.dx * p->scale_down * p->scale_down;
+    if (p->pb.physics == HW_ACOUSTIC2D) {
+        e = launch_ac2d_energy((const Ac2dDesc *)p->d_desc, p->cur, p->pb.ny,
+                               p->pb.storage, p->pb.order, p->partial, s);
+    } else {
+        factor *= p->pb.dx;
+        e = launch_el3d_energy((const El3dDesc *)p->d_desc, p->L.rows,
+                               p->pb.storage, p->partial, s);
+    }
+    if (e == hipSuccess)
+        e = launch_energy_finish(p->partial, p->L.rows, factor,
+                                 p->trace + p->trace_n, p->flags, s);
+    if (e != hipSuccess)
+        return fail(HW_E_DEVICE, std::string("energy launch: ") + hipGetErrorString(e));
+    p->trace_steps.push_back(p->step);
+    p->trace_n += 1;
+    p->last_logged = p->step;
+    return HW_OK;
+}
+
+int64_t logs_needed(const hw_plan *p, int64_t nsteps, int64_t every)
+{
+    if (every <= 0)
+        return 0;
+    int64_t first = p->step + (every - p->step % every) % every;   // >= step
+    int64_t last = p->step + nsteps;
+    if (first > last)
+        return 0;
+    int64_t cnt = (last - first) / every + 1;
+    if (first == p->last_logged)
+        cnt -= 1;
+    return cnt;
+}
+
+hw_status check_ready(const hw_plan *p)
+{
+    if (!p)
+        return fail(HW_E_INVAL, "plan is NULL");
+    if (!p->have_material || !p->have_fields)
+        return fail(HW_E_STATE, "material and fields must be uploaded first");
+    return HW_OK;
+}
+
+hw_status host_fields_in_range(const hw_plan *p, const double *const *fields)
+{
+    const double maxv = max_finite(p->pb.storage);
+    for (int f = 0; f < p->L.nf; ++f) {
+        const double *a = fields[f];
+        if (!a)
+            continue;
+        for (int64_t i = 0; i < p->L.cells; ++i) {
+            const double v = a[i] * p->scale_up;
+            if (!std::isfinite(v) || std::fabs(v) > maxv)
+                return fail(HW_E_RANGE, "field " + std::to_string(f) + " value " +
+                                            std::to_string(a[i]) + " at " +
+                                            std::to_string(i) +
+                                            " does not fit the storage format");
+        }
+    }
+    return HW_OK;
+}
+
+hw_status host_material_ok(const hw_plan *p, const double *const *mat)
+{
+    const hw_problem &pb = p->pb;
+    const int64_t nx = pb.nx, ny = pb.ny, nz = pb.nz, n = p->L.cells;
+    for (int m = 0; m < p->L.nm; ++m)
+        if (!mat[m])
+            return fail(HW_E_INVAL, "material array " + std::to_string(m) + " is NULL");
+    for (int64_t i = 0; i < n; ++i) {
+        const double rho = mat[0][i];
+        if (!std::isfinite(rho) || !(rho > 0) || !std::isfinite((float)(1.0 / rho)) ||
+            (float)(1.0 / rho) == 0.0f)
+            return fail(HW_E_INVAL, "rho must be finite, > 0 and 1/rho must fit fp32");
+        for (int m = 1; m < p->L.nm; ++m)
+            if (!std::isfinite(mat[m][i]) || !std::isfinite((float)mat[m][i]))
+                return fail(HW_E_INVAL, "material values must be finite in fp32");
+        if (pb.physics == HW_ACOUSTIC2D) {
+            if (!(mat[1][i] > 0))
+                return fail(HW_E_INVAL, "kappa must be > 0");
+        } else {
+            const double lam = mat[1][i], mu = mat[2][i];
+            if (!(mu > 0) || !(3 * lam + 2 * mu > 0))
+                return fail(HW_E_INVAL, "need mu > 0 and 3 lambda + 2 mu > 0");
+        }
+    }
+    // Courant number: for every face, staggered buoyancy times the larger
+    // modulus of the two cells it joins.
+    double c2max = 0.0;
+    auto idx = [&](int64_t i, int64_t j, int64_t k) {
+        return ((k % nz) * ny + (j % ny)) * nx + (i % nx);
+    };
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t q = idx(i, j, k);
+                const int64_t nb[3] = {idx(i + 1, j, k), idx(i, j + 1, k), idx(i, j, k + 1)};
+                const int naxes = pb.physics == HW_ACOUSTIC2D ? 2 : 3;
+                for (int a = 0; a < naxes; ++a) {
+                    const int64_t r = nb[a];
+                    const double bf = 0.5 * (1.0 / mat[0][q] + 1.0 / mat[0][r]);
+                    double mq, mr;
+                    if (pb.physics == HW_ACOUSTIC2D) {
+                        mq = mat[1][q];
+                        mr = mat[1][r];
+                    } else {
+                        mq = mat[1][q] + 2 * mat[2][q];
+                        mr = mat[1][r] + 2 * mat[2][r];
+                    }
+                    c2max = std::max(c2max, bf * std::max(mq, mr));
+                }
+            }
+    const double cfl = std::sqrt(c2max) * pb.dt / pb.dx;
+    const double bound = cfl_bound(pb.physics, pb.order);
+    if (!(cfl < bound))
+        return fail(HW_E_UNSTABLE, "Courant number " + std::to_string(cfl) +
+                                       " is not below the stability bound " +
+                                       std::to_string(bound));
+    return HW_OK;
+}
+
+hw_status upload_desc(hw_plan *p, hipStream_t s)
+{
+    const void *src = p->pb.physics == HW_ACOUSTIC2D ? (const void *)&p->h2
+                                                      : (const void *)&p->h3;
+    const size_t n = p->pb.physics == HW_ACOUSTIC2D ? sizeof(Ac2dDesc) : sizeof(El3dDesc);
+    HW_HIP(hipMemcpyAsync(p->d_desc, src, n, hipMemcpyHostToDevice, s));
+    return HW_OK;
+}
+
+hw_status advance_one(hw_plan *p, int64_t nsteps, int64_t every, hipStream_t s)
+{
+    hw_status st;
+    if (every > 0 && p->step % every == 0 && p->last_logged != p->step)
+        if ((st = record_energy(p, s)) != HW_OK)
+            return st;
+    hw_plan *pl[1] = {p};
+    for (int64_t n = 0; n < nsteps; ++n) {
+        if ((st = launch_group(pl, 1, p->tile, s)) != HW_OK)
+            return st;
+        if (every > 0 && p->step % every == 0)
+            if ((st = record_energy(p, s)) != HW_OK)
+                return st;
+    }
+    return HW_OK;
+}
+
+struct BlobHeader {
+    char magic[8];
+    uint32_t abi;
+    int32_t physics, order, storage, comp, scale_log2;
+    int64_t nx, ny, nz, step;
+    uint64_t field_bytes;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI --
+
+extern "C" {
+
+uint32_t hw_abi_version(void) { return HW_ABI_VERSION; }
+
+const char *hw_last_error(void) { return g_error.c_str(); }
+
+int32_t hw_num_fields(int32_t physics)
+{
+    return physics == HW_ACOUSTIC2D ? 3 : physics == HW_ELASTIC3D ? 9 : 0;
+}
+
+int32_t hw_num_materials(int32_t physics)
+{
+    return physics == HW_ACOUSTIC2D ? 2 : physics == HW_ELASTIC3D ? 3 : 0;
+}
+
+double hw_cfl_bound(int32_t physics, int32_t order) { return cfl_bound(physics, order); }
+
+hw_status hw_footprint(const hw_problem *pb, size_t *device_bytes)
+{
+    hw_status st = validate(pb);
+    if (st != HW_OK)
+        return st;
+    if (!device_bytes)
+        return fail(HW_E_INVAL, "device_bytes is NULL");
+    *device_bytes = make_layout(pb).total;
+    return HW_OK;
+}
+
+hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
+                         hw_plan **out)
+{
+    hw_status st = validate(pb);
+    if (st != HW_OK)
+        return st;
+    if (!out)
+        return fail(HW_E_INVAL, "out is NULL");
+    if (!arena || ((uintptr_t)arena % kAlign) != 0)
+        return fail(HW_E_INVAL, "arena must be a non-NULL 256-byte aligned device pointer");
+    const Layout L = make_layout(pb);
+    if (arena_bytes < L.total)
+        return fail(HW_E_NOMEM, "arena has " + std::to_string(arena_bytes) +
+                                    " bytes, the plan needs " + std::to_string(L.total));
+    hw_plan *p = new (std::nothrow) hw_plan();
+    if (!p)
+        return fail(HW_E_NOMEM, "host allocation failed");
+    p->pb = *pb;
+    p->L = L;
+    p->arena = (char *)arena;
+    for (int s = 0; s < 2; ++s)
+        for (int f = 0; f < 9; ++f) {
+            const int ss = s < L.sets ? s : 0;
+            p->fld[s][f] = f < L.nf ? p->arena + L.off_fld[ss][f] : nullptr;
+            p->cmp[s][f] = (f < L.nf && pb->comp != HW_COMP_NONE)
+                               ? p->arena + L.off_cmp[ss][f] : nullptr;
+        }
+    for (int m = 0; m < 3; ++m)
+        p->mat[m] = m < L.nm ? (float *)(p->arena + L.off_mat[m]) : nullptr;
+    p->staging = (double *)(p->arena + L.off_staging);
+    p->partial = (double *)(p->arena + L.off_partial);
+    p->trace = (double *)(p->arena + L.off_trace);
+    p->flags = (int32_t *)(p->arena + L.off_flags);
+    p->d_desc = p->arena + L.off_desc;
+    p->scale_up = std::ldexp(1.0, pb->scale_log2);
+    p->scale_down = std::ldexp(1.0, -pb->scale_log2);
+    const double r = pb->dt / pb->dx;
+    if (pb->physics == HW_ACOUSTIC2D) {
+        Ac2dDesc &d = p->h2;
+        std::memset(&d, 0, sizeof(d));
+        d.nx = pb->nx;
+        d.ny = pb->ny;
+        d.pitch = L.pitch;
+        d.w1 = pb->order == 4 ? (float)((9.0 / 8.0) * r) : (float)(1.0 * r);
+        d.w2 = pb->order == 4 ? (float)((-1.0 / 24.0) * r) : 0.0f;
+        d.b = p->mat[0];
+        d.k = p->mat[1];
+        for (int s = 0; s < 2; ++s) {
+            d.vx[s] = p->fld[s][0];
+            d.vy[s] = p->fld[s][1];
+            d.p[s] = p->fld[s][2];
+            d.cvx[s] = p->cmp[s][0];
+            d.cvy[s] = p->cmp[s][1];
+        }
+        d.cp = p->cmp[0][2];
+    } else {
+        El3dDesc &d = p->h3;
+        std::memset(&d, 0, sizeof(d));
+        d.nx = pb->nx;
+        d.ny = pb->ny;
+        d.nz = pb->nz;
+        d.pitch = L.pitch;
+        d.slab = L.slab;
+        d.w = (float)(1.0 * r);
+        d.b = p->mat[0];
+        d.lam = p->mat[1];
+        d.mu = p->mat[2];
+        for (int f = 0; f < 9; ++f) {
+            d.f[f] = p->fld[0][f];
+            d.c[f] = p->cmp[0][f];
+        }
+    }
+    *out = p;
+    return HW_OK;
+}
+
+void hw_plan_destroy(hw_plan *plan) { delete plan; }
+
+hw_status hw_set_material(hw_plan *p, const double *const *material, void *stream)
+{
+    if (!p || !material)
+        return fail(HW_E_INVAL, "plan or material is NULL");
+    hw_status st = host_material_ok(p, material);
+    if (st != HW_OK)
+        return st;
+    hipStream_t s = S(stream);
+    const int64_t nx = p->pb.nx;
+    for (int m = 0; m < p->L.nm; ++m) {
+        HW_HIP(hipMemcpyAsync(p->staging, material[m], (size_t)p->L.cells * 8,
+                              hipMemcpyHostToDevice, s));
+        HW_HIP(launch_material(p->staging, p->mat[m], m == 0, nx, p->L.rows,
+                               p->L.pitch, s));
+    }
+    if ((st = upload_desc(p, s)) != HW_OK)
+        return st;
+    p->have_material = true;
+    return HW_OK;
+}
+
+hw_status hw_set_fields(hw_plan *p, const double *const *fields, void *stream)
+{
+    if (!p || !fields)
+        return fail(HW_E_INVAL, "plan or fields is NULL");
+    hw_status st = host_fields_in_range(p, fields);
+    if (st != HW_OK)
+        return st;
+    hipStream_t s = S(stream);
+    for (int f = 0; f < p->L.nf; ++f) {
+        if (!fields[f]) {
+            HW_HIP(launch_fill_zero(p->fld[0][f], p->L.field_bytes, s));
+            continue;
+        }
+        HW_HIP(hipMemcpyAsync(p->staging, fields[f], (size_t)p->L.cells * 8,
+                              hipMemcpyHostToDevice, s));
+        HW_HIP(launch_to_storage(p->staging, p->fld[0][f], p->pb.storage, p->pb.nx,
+                                 p->L.rows, p->L.pitch, p->scale_up, s));
+    }
+    if (p->pb.comp != HW_COMP_NONE)
+        for (int set = 0; set < p->L.sets; ++set)
+            for (int f = 0; f < p->L.nf; ++f)
+                HW_HIP(launch_fill_zero(p->cmp[set][f], p->L.field_bytes, s));
+    HW_HIP(launch_fill_zero(p->flags, kAlign, s));
+    if ((st = upload_desc(p, s)) != HW_OK)
+        return st;
+    p->cur = 0;
+    p->step = 0;
+    p->trace_n = 0;
+    p->last_logged = -1;
+    p->trace_steps.clear();
+    p->have_fields = true;
+    return HW_OK;
+}
+
+hw_status hw_advance(hw_plan *p, int64_t nsteps, int64_t energy_every, void *stream)
+{
+    hw_status st = check_ready(p);
+    if (st != HW_OK)
+        return st;
+    if (nsteps < 0)
+        return fail(HW_E_INVAL, "nsteps must be >= 0");
+    if (p->trace_n + logs_needed(p, nsteps, energy_every) > p->pb.trace_cap)
+        return fail(HW_E_NOMEM, "energy trace capacity too small for this advance");
+    return advance_one(p, nsteps, energy_every, S(stream));
+}
+
+hw_status hw_record_energy(hw_plan *p, void *stream)
+{
+    hw_status st = check_ready(p);
+    if (st != HW_OK)
+        return st;
+    return record_energy(p, S(stream));
+}
+
+hw_status hw_energy_trace(hw_plan *p, double *energy, int64_t *step, int64_t cap,
+                          int64_t *n_out, void *stream)
+{
+    if (!p)
+        return fail(HW_E_INVAL, "plan is NULL");
+    hipStream_t s = S(stream);
+    std::vector<double> e((size_t)std::max<int64_t>(p->trace_n, 1));
+    int32_t flag = 0;
+    if (p->trace_n > 0)
+        HW_HIP(hipMemcpyAsync(e.data(), p->trace, (size_t)p->trace_n * 8,
+                              hipMemcpyDeviceToHost, s));
+    HW_HIP(hipMemcpyAsync(&flag, p->flags, 4, hipMemcpyDeviceToHost, s));
+    HW_HIP(hipStreamSynchronize(s));
+    const int64_t n = std::min(cap, p->trace_n);
+    for (int64_t k = 0; k < n; ++k) {
+        if (energy)
+            energy[k] = e[k];
+        if (step)
+            step[k] = p->trace_steps[k];
+    }
+    if (n_out)
+        *n_out = p->trace_n;
+    if (flag)
+        return fail(HW_E_NONFINITE, "the state became non-finite");
+    return HW_OK;
+}
+
+hw_status hw_get_fields(hw_plan *p, double *const *fields, double *const *comps,
+                        void *stream)
+{
+    hw_status st = check_ready(p);
+    if (st != HW_OK)
+        return st;
+    hipStream_t s = S(stream);
+    const size_t bytes = (size_t)p->L.cells * 8;
+    for (int pass = 0; pass < 2; ++pass) {
+        double *const *dst = pass == 0 ? fields : comps;
+        if (!dst)
+            continue;
+        for (int f = 0; f < p->L.nf; ++f) {
+            if (!dst[f])
+                continue;
+            if (pass == 1 && p->pb.comp == HW_COMP_NONE) {
+                std::memset(dst[f], 0, bytes);
+                continue;
+            }
+            const void *src = pass == 0 ? p->fld[p->cur][f] : p->cmp[p->cur][f];
+            HW_HIP(launch_from_storage(src, p->staging, p->pb.storage, p->pb.nx,
+                                       p->L.rows, p->L.pitch, p->scale_down, s));
+            HW_HIP(hipMemcpyAsync(dst[f], p->staging, bytes, hipMemcpyDeviceToHost, s));
+        }
+    }
+    int32_t flag = 0;
+    HW_HIP(hipMemcpyAsync(&flag, p->flags, 4, hipMemcpyDeviceToHost, s));
+    HW_HIP(hipStreamSynchronize(s));
+    if (flag)
+        return fail(HW_E_NONFINITE, "the state became non-finite");
+    return HW_OK;
+}
+
+int64_t hw_plan_step(const hw_plan *p) { return p ? p->step : -1; }
+
+hw_status hw_state_size(const hw_plan *p, size_t *bytes)
+{
+    if (!p || !bytes)
+        return fail(HW_E_INVAL, "plan or bytes is NULL");
+    const int ncomp = p->pb.comp != HW_COMP_NONE ? p->L.nf : 0;
+    *bytes = sizeof(BlobHeader) + (size_t)(p->L.nf + ncomp) * p->L.field_bytes;
+    return HW_OK;
+}
+
+hw_status hw_state_export(hw_plan *p, void *blob, size_t bytes, void *stream)
+{
+    hw_status st = check_ready(p);
+    if (st != HW_OK)
+        return st;
+    size_t need;
+    hw_state_size(p, &need);
+    if (!blob || bytes < need)
+        return fail(HW_E_INVAL, "blob too small");
+    BlobHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, "HWSTATE1", 8);
+    h.abi = HW_ABI_VERSION;
+    h.physics = p->pb.physics;
+    h.order = p->pb.order;
+    h.storage = p->pb.storage;
+    h.comp = p->pb.comp;
+    h.scale_log2 = p->pb.scale_log2;
+    h.nx = p->pb.nx;
+    h.ny = p->pb.ny;
+    h.nz = p->pb.nz;
+    h.step = p->step;
+    h.field_bytes = p->L.field_bytes;
+    std::memcpy(blob, &h, sizeof(h));
+    char *dst = (char *)blob + sizeof(h);
+    hipStream_t s = S(stream);
+    for (int f = 0; f < p->L.nf; ++f, dst += p->L.field_bytes)
+        HW_HIP(hipMemcpyAsync(dst, p->fld[p->cur][f], p->L.field_bytes,
+                              hipMemcpyDeviceToHost, s));
+    if (p->pb.comp != HW_COMP_NONE)
+        for (int f = 0; f < p->L.nf; ++f, dst += p->L.field_bytes)
+            HW_HIP(hipMemcpyAsync(dst, p->cmp[p->cur][f], p->L.field_bytes,
+                                  hipMemcpyDeviceToHost, s));
+    HW_HIP(hipStreamSynchronize(s));
+    return HW_OK;
+}
+
+hw_status hw_state_import(hw_plan *p, const void *blob, size_t bytes, void *stream)
+{
+    if (!p || !blob)
+        return fail(HW_E_INVAL, "plan or blob is NULL");
+    if (!p->have_material)
+        return fail(HW_E_STATE, "upload the material before importing a state");
+    size_t need;
+    hw_state_size(p, &need);
+    if (bytes < need)
+        return fail(HW_E_INVAL, "blob too small");
+    BlobHeader h;
+    std::memcpy(&h, blob, sizeof(h));
+    if (std::memcmp(h.magic, "HWSTATE1", 8) != 0 || h.abi != HW_ABI_VERSION ||
+        h.physics != p->pb.physics || h.order != p->pb.order ||
+        h.storage != p->pb.storage || h.comp != p->pb.comp ||
+        h.scale_log2 != p->pb.scale_log2 || h.nx != p->pb.nx ||
+        h.ny != p->pb.ny || h.nz != p->pb.nz ||
+        h.field_bytes != p->L.field_bytes || h.step < 0)
+        return fail(HW_E_INVAL, "blob does not match this plan's problem");
+    hipStream_t s = S(stream);
+    const char *src = (const char *)blob + sizeof(h);
+    for (int f = 0; f < p->L.nf; ++f, src += p->L.field_bytes)
+        HW_HIP(hipMemcpyAsync(p->fld[0][f], src, p->L.field_bytes,
+                              hipMemcpyHostToDevice, s));
+    if (p->pb.comp != HW_COMP_NONE)
+        for (int f = 0; f < p->L.nf; ++f, src += p->L.field_bytes)
+            HW_HIP(hipMemcpyAsync(p->cmp[0][f], src, p->L.field_bytes,
+                                  hipMemcpyHostToDevice, s));
+    HW_HIP(launch_fill_zero(p->flags, kAlign, s));
+    HW_HIP(hipStreamSynchronize(s));
+    p->cur = 0;
+    p->step = h.step;
+    p->trace_n = 0;
+    p->last_logged = -1;
+    p->trace_steps.clear();
+    p->have_fields = true;
+    return HW_OK;
+}
+
+int32_t hw_tile_count(int32_t physics)
+{
+    return physics == HW_ACOUSTIC2D ? kNumTiles2D : physics == HW_ELASTIC3D ? kNumTiles3D : 0;
+}
+
+hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx, int32_t *ty)
+{
+    if (tile < 0 || tile >= hw_tile_count(physics))
+        return fail(HW_E_INVAL, "tile index out of range");
+    const TileShape t = physics == HW_ACOUSTIC2D ? kTiles2D[tile] : kTiles3D[tile];
+    if (tx)
+        *tx = t.tx;
+    if (ty)
+        *ty = t.ty;
+    return HW_OK;
+}
+
+hw_status hw_plan_set_tile(hw_plan *p, int32_t tile)
+{
+    if (!p)
+        return fail(HW_E_INVAL, "plan is NULL");
+    if (tile < 0 || tile >= num_tiles(p->pb))
+        return fail(HW_E_INVAL, "tile index out of range");
+    p->tile = tile;
+    return HW_OK;
+}
+
+hw_status hw_batch_advance(hw_plan *const *plans, int32_t n, const int64_t *nsteps,
+                           int64_t energy_every, int32_t tile, void *stream)
+{
+    if (!plans || !nsteps || n <= 0)
+        return fail(HW_E_INVAL, "need n > 0 plans and their step counts");
+    for (int i = 0; i < n; ++i) {
+        hw_status st = check_ready(plans[i]);
+        if (st != HW_OK)
+            return st;
+        if (nsteps[i] < 0)
+            return fail(HW_E_INVAL, "nsteps must be >= 0");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i])
+                return fail(HW_E_INVAL, "plans must be distinct");
+        if (plans[i]->trace_n + logs_needed(plans[i], nsteps[i], energy_every) >
+            plans[i]->pb.trace_cap)
+            return fail(HW_E_NOMEM, "energy trace capacity too small for plan " +
+                                        std::to_string(i));
+        if (tile >= num_tiles(plans[i]->pb))
+            return fail(HW_E_INVAL, "tile index out of range");
+    }
+    hipStream_t s = S(stream);
+    hw_status st;
+    std::vector<int64_t> left(nsteps, nsteps + n);
+    for (int i = 0; i < n; ++i) {
+        hw_plan *p = plans[i];
+        if (energy_every > 0 && p->step % energy_every == 0 && p->last_logged != p->step)
+            if ((st = record_energy(p, s)) != HW_OK)
+                return st;
+    }
+    for (;;) {
+        std::map<KernelKey, std::vector<hw_plan *>> groups;
+        std::vector<int> active;
+        for (int i = 0; i < n; ++i)
+            if (left[i] > 0) {
+                groups[plans[i]->key()].push_back(plans[i]);
+                active.push_back(i);
+            }
+        if (active.empty())
+            break;
+        for (auto &g : groups) {
+            const int t = tile >= 0 ? tile : g.second[0]->tile;
+            if ((st = launch_group(g.second.data(), (int)g.second.size(), t, s)) != HW_OK)
+                return st;
+        }
+        for (int i : active) {
+            left[i] -= 1;
+            hw_plan *p = plans[i];
+            if (energy_every > 0 && p->step % energy_every == 0)
+                if ((st = record_energy(p, s)) != HW_OK)
+                    return st;
+        }
+    }
+    return HW_OK;
+}
+
+hw_status hw_simulate(const hw_problem *pb, const double *const *material,
+                      double *const *fields, int64_t nsteps, int64_t energy_every,
+                      double *energy, int64_t energy_cap, int64_t *n_energy,
+                      void *arena, size_t arena_bytes, void *stream)
+{
+    if (!fields)
+        return fail(HW_E_INVAL, "fields is NULL");
+    hw_plan *p = nullptr;
+    hw_status st = hw_plan_create(pb, arena, arena_bytes, &p);
+    if (st != HW_OK)
+        return st;
+    const double *const *in = (const double *const *)fields;
+    if ((st = hw_set_material(p, material, stream)) == HW_OK &&
+        (st = hw_set_fields(p, in, stream)) == HW_OK &&
+        (st = hw_advance(p, nsteps, energy_every, stream)) == HW_OK &&
+        (st = hw_get_fields(p, fields, nullptr, stream)) == HW_OK)
+        st = hw_energy_trace(p, energy, nullptr, energy_cap, n_energy, stream);
+    hw_plan_destroy(p);
+    return st;
+}
+
+}  // extern "C"

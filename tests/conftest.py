@@ -20,3 +20,13 @@ def _oracle_built():
     import oracle
     oracle.build(force=False)
     yield
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _library_built():
+    """Load the built HIP library; build it only if nothing is built yet."""
+    import paper_2310_00236_amd as hw
+    if not os.path.exists(hw.LIB_PATH):
+        from paper_2310_00236_amd import build
+        build.build()
+    yield

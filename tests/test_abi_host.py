@@ -1,0 +1,174 @@
+"""Host-side tests of the C ABI (no GPU needed): the library loads, exports
+every entry point its header declares, and validates problems, materials and
+fields before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2310_00236_amd as hw
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include",
+                      "halfwave.h")
+FAKE_ARENA = 1 << 20      # aligned non-NULL address; never dereferenced here
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hw_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 20
+    hw.lib()                      # loads torch's HIP runtime first
+    L = ctypes.CDLL(hw.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_abi_version_and_counts():
+    L = hw.lib()
+    assert L.hw_abi_version() == hw.ABI_VERSION
+    assert L.hw_num_fields(0) == 3 and L.hw_num_fields(1) == 9
+    assert L.hw_num_materials(0) == 2 and L.hw_num_materials(1) == 3
+    assert L.hw_num_fields(7) == 0
+
+
+def test_cfl_bounds():
+    assert hw.cfl_bound("acoustic2d", 2) == pytest.approx(2 ** -0.5)
+    assert hw.cfl_bound("acoustic2d", 4) == pytest.approx(1 / (2 ** 0.5 * (9 / 8 + 1 / 24)))
+    assert hw.cfl_bound("elastic3d", 2) == pytest.approx(3 ** -0.5)
+    assert hw.lib().hw_cfl_bound(1, 4) < 0
+
+
+def test_tiles_listed():
+    t2, t3 = hw.tiles("acoustic2d"), hw.tiles("elastic3d")
+    assert len(t2) >= 2 and len(t3) >= 2
+    assert all(tx * ty in (256, 512, 1024, 2048) for tx, ty in t2)
+    assert all(tx * ty == 256 for tx, ty in t3)
+
+
+def _pb(**kw):
+    base = dict(physics="acoustic2d", nx=32, ny=24, nz=1, order=4, storage="f16",
+                comp="twosum", dx=1.0, dt=0.1, scale_log2=0, trace_cap=4)
+    base.update(kw)
+    return hw.Problem(**base)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=0), dict(ny=-1), dict(nz=2), dict(order=3), dict(order=6),
+    dict(physics="elastic3d", nz=4, order=4), dict(dt=0.0), dict(dx=-1.0),
+    dict(dt=float("nan")), dict(trace_cap=-1), dict(scale_log2=61),
+])
+def test_invalid_problems(kw):
+    with pytest.raises(hw.HalfwaveError) as ei:
+        hw.footprint(_pb(**kw))
+    assert ei.value.name == "HW_E_INVAL"
+
+
+def test_invalid_enums_and_abi():
+    for field, val in (("storage", 7), ("comp", 5), ("physics", 3),
+                       ("abi_version", 99)):
+        c = _pb().c()
+        setattr(c, field, val)
+        n = ctypes.c_size_t()
+        assert hw.lib().hw_footprint(ctypes.byref(c), ctypes.byref(n)) == 1
+
+
+def test_footprint_grows_with_precision_and_compensation():
+    f16 = hw.footprint(_pb(storage="f16", comp="none"))
+    f16c = hw.footprint(_pb(storage="f16", comp="twosum"))
+    f32 = hw.footprint(_pb(storage="f32", comp="none"))
+    assert f16 < f16c and f16 < f32
+
+
+def _plan(pb, arena_bytes=None):
+    h = ctypes.c_void_p()
+    n = hw.footprint(pb) if arena_bytes is None else arena_bytes
+    st = hw.lib().hw_plan_create(ctypes.byref(pb.c()), ctypes.c_void_p(FAKE_ARENA),
+                                 n, ctypes.byref(h))
+    return st, h
+
+
+def test_plan_create_checks_arena():
+    pb = _pb()
+    st, _ = _plan(pb, hw.footprint(pb) - 1)
+    assert st == 4                                   # HW_E_NOMEM
+    h = ctypes.c_void_p()
+    st = hw.lib().hw_plan_create(ctypes.byref(pb.c()), ctypes.c_void_p(FAKE_ARENA + 8),
+                                 hw.footprint(pb), ctypes.byref(h))
+    assert st == 1 and not h.value                   # misaligned: INVAL
+    st, h = _plan(pb)
+    assert st == 0 and h.value
+    hw.lib().hw_plan_destroy(h)
+
+
+def _set(fn, h, arrays):
+    P = ctypes.POINTER(ctypes.c_double)
+    keep = [np.ascontiguousarray(a, dtype=np.float64) if a is not None else None
+            for a in arrays]
+    ptrs = (P * len(keep))(*[a.ctypes.data_as(P) if a is not None else P()
+                             for a in keep])
+    return fn(h, ptrs, None)
+
+
+@pytest.mark.parametrize("mat,status", [
+    ("rho0", 1), ("kappa_neg", 1), ("nan", 1), ("unstable", 2)])
+def test_material_validation_before_device(mat, status):
+    pb = _pb(dt=0.2)
+    st, h = _plan(pb)
+    rho = np.ones((24, 32))
+    kappa = np.ones((24, 32))
+    if mat == "rho0":
+        rho[3, 4] = 0.0
+    elif mat == "kappa_neg":
+        kappa[5, 5] = -1.0
+    elif mat == "nan":
+        kappa[0, 0] = np.nan
+    elif mat == "unstable":
+        kappa[10, 10] = 20.0        # c = 4.5 at one cell: CFL 0.9 > 0.606
+    assert _set(hw.lib().hw_set_material, h, [rho, kappa]) == status
+    hw.lib().hw_plan_destroy(h)
+
+
+def test_elastic_material_validation():
+    pb = _pb(physics="elastic3d", nx=8, ny=6, nz=5, order=2, dt=0.1)
+    st, h = _plan(pb)
+    one = np.ones((5, 6, 8))
+    mu = one.copy()
+    mu[1, 1, 1] = 0.0
+    assert _set(hw.lib().hw_set_material, h, [one, one, mu]) == 1
+    lam = one.copy()
+    lam[2, 2, 2] = -0.7             # 3 lambda + 2 mu < 0
+    assert _set(hw.lib().hw_set_material, h, [one, lam, one]) == 1
+    assert _set(hw.lib().hw_set_material, h, [one, one, 40 * one]) == 2
+    hw.lib().hw_plan_destroy(h)
+
+
+@pytest.mark.parametrize("storage,value,scale,status", [
+    ("f16", 65504.0, 0, None), ("f16", 65505.0, 0, 3), ("f16", np.inf, 0, 3),
+    ("f16", np.nan, 0, 3), ("f16", 1100.0, 6, 3), ("f16", 1000.0, 6, None), ("bf16", 1e38, 0, None),
+    ("bf16", 3.4e38, 0, 3), ("f32", 1e39, 0, 3)])
+def test_field_range_validation(storage, value, scale, status):
+    pb = _pb(storage=storage, scale_log2=scale)
+    st, h = _plan(pb)
+    p = np.zeros((24, 32))
+    p[1, 2] = value
+    got = _set(hw.lib().hw_set_fields, h, [None, None, p])
+    if status is None:
+        assert got != 3             # passes validation (then needs a device)
+    else:
+        assert got == status
+        assert b"does not fit" in hw.lib().hw_last_error()
+    hw.lib().hw_plan_destroy(h)
+
+
+def test_advance_before_upload_is_state_error():
+    st, h = _plan(_pb())
+    assert hw.lib().hw_advance(h, 1, 0, None) == 7
+    assert hw.lib().hw_plan_step(h) == 0
+    hw.lib().hw_plan_destroy(h)

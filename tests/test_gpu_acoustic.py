@@ -1,0 +1,186 @@
+"""GPU parity of the 2D acoustic path (through the C ABI) against the oracle.
+
+Bit-exact against the oracle's op-by-op emulation of every storage format
+and compensation mode, on grids that span several tiles with ragged tails,
+on tiny grids where the stencil wraps several times, for every compiled tile
+shape; within the stated tolerances against the FP64 reference (relative
+energy drift and relative L2 field error) on the small homogeneous workload.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2310_00236_amd as hw
+import workloads
+from helpers import (ST, acoustic_fields, assert_bitexact, gpu_acoustic,
+                     layered_material, oracle_acoustic, rel_drift, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("storage", ST)
+@pytest.mark.parametrize("comp", ["none", "fast2sum", "twosum"])
+@pytest.mark.parametrize("order", [2, 4])
+def test_bitexact_vs_emulation(storage, comp, order):
+    nx, ny = 150, 37           # 3 x 3 tiles of 64 x 16 with ragged tails
+    rho, kappa, c = layered_material(nx, ny, 101)
+    dt = 0.45 * hw.cfl_bound("acoustic2d", order) / c
+    f = acoustic_fields(nx, ny, 102, storage)
+    g, gc, ge = gpu_acoustic(nx, ny, order, storage, comp, dt, rho, kappa, f, 25,
+                             energy_every=5)
+    w, wc, we = oracle_acoustic(nx, ny, order, storage, comp, dt, rho, kappa, f,
+                                25, energy_every=5)
+    assert_bitexact(g, w, "fields")
+    if comp != "none":
+        assert_bitexact(gc, wc, "comps")
+    # the energy is an fp64 sum over cells in another order
+    np.testing.assert_allclose(ge, we, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 5), (4, 4), (5, 7), (7, 3),
+                                   (64, 16), (65, 17), (257, 3), (3, 130)])
+@pytest.mark.parametrize("tile", range(5))
+def test_bitexact_sizes_and_tiles(shape, tile):
+    nx, ny = shape
+    rho, kappa, c = layered_material(nx, ny, 103)
+    dt = 0.4 * hw.cfl_bound("acoustic2d", 4) / c
+    f = acoustic_fields(nx, ny, 104, "f16")
+    g, gc, _ = gpu_acoustic(nx, ny, 4, "f16", "twosum", dt, rho, kappa, f, 9,
+                            tile=tile)
+    w, wc, _ = oracle_acoustic(nx, ny, 4, "f16", "twosum", dt, rho, kappa, f, 9)
+    assert_bitexact(g, w, f"{shape} tile {tile}")
+    assert_bitexact(gc, wc, f"{shape} tile {tile} comps")
+
+
+def test_small_homogeneous_workload_parity():
+    """128x128, order 2, CFL 0.5, centred Gaussian, 1000 steps, energy every
+    step: bit-exact against the emulation for fp16 plain and compensated, and
+    within tolerance of the FP64 reference started from the same rounded
+    initial state (so only the time stepping's roundoff is measured)."""
+    w = workloads.small2d()
+    f = w.fields()
+    args = (w.nx, w.ny, w.order)
+    refs = {}
+    for storage in ("f32", "f16", "bf16"):
+        fr = {k: oracle.round_to(v, storage) for k, v in f.items()}
+        refs[storage] = oracle_acoustic(*args, "f64", "none", w.dt, w.rho,
+                                        w.kappa, fr, w.nsteps, energy_every=1)
+    results = {}
+    for storage, comp in (("f32", "none"), ("f16", "none"), ("f16", "twosum"),
+                          ("f16", "fast2sum"), ("bf16", "twosum")):
+        g, _, ge = gpu_acoustic(*args, storage, comp, w.dt, w.rho, w.kappa, f,
+                                w.nsteps, energy_every=1)
+        results[(storage, comp)] = (g, ge)
+        if storage == "f16":
+            o, _, _ = oracle_acoustic(*args, storage, comp, w.dt, w.rho, w.kappa,
+                                      f, w.nsteps)
+            assert_bitexact(g, o, f"{storage}+{comp}")
+    g32, e32 = results[("f32", "none")]
+    assert rel_drift(e32, refs["f32"][2]) <= 1e-5
+    assert rel_l2(g32, refs["f32"][0]) <= 1e-4
+    for comp in ("twosum", "fast2sum"):
+        g16c, e16c = results[("f16", comp)]
+        assert rel_drift(e16c, refs["f16"][2]) <= 1e-3
+        assert rel_l2(g16c, refs["f16"][0]) <= 5e-2
+
+
+def test_compensation_fixes_energy_loss_small_cfl():
+    """At a small Courant number plain fp16 loses energy and the compensated
+    update does not (Sec. 3, Sec. 4), on the GPU."""
+    n = 96
+    w = workloads.small2d(n, nsteps=4000, order=4, cfl=0.0125, sigma=6.0)
+    f = w.fields()
+    _, _, e64 = oracle_acoustic(n, n, 4, "f64", "none", w.dt, w.rho, w.kappa,
+                                {k: oracle.round_to(v, "f16") for k, v in f.items()},
+                                w.nsteps, energy_every=500)
+    _, _, e16 = gpu_acoustic(n, n, 4, "f16", "none", w.dt, w.rho, w.kappa, f,
+                             w.nsteps, energy_every=500)
+    _, _, e6 = gpu_acoustic(n, n, 4, "f16", "twosum", w.dt, w.rho, w.kappa, f,
+                            w.nsteps, energy_every=500)
+    loss = (e16[-1] - e64[0]) / e64[0]
+    assert loss < -1e-2
+    assert rel_drift(e6, e64) < 0.05 * abs(loss)
+
+
+def test_symmetry_bit_exact_on_gpu():
+    n = 128
+    w = workloads.small2d(n, nsteps=300)
+    g, _, _ = gpu_acoustic(n, n, 2, "f16", "none", w.dt, w.rho, w.kappa,
+                           w.fields(), w.nsteps)
+    c = n // 2
+    idx = (2 * c - np.arange(n)) % n
+    vidx = (2 * c - 1 - np.arange(n)) % n
+    assert np.array_equal(g["p"], g["p"][:, idx])
+    assert np.array_equal(g["p"], g["p"].T)
+    assert np.array_equal(g["vx"], -g["vx"][:, vidx])
+    assert np.array_equal(g["vx"], g["vy"].T)
+
+
+def test_power_of_two_field_scale_is_exact():
+    """Holding the fields scaled by 2^k (Sec. 5, range) gives the same
+    results as the emulation run on scaled inputs, returned unscaled."""
+    nx, ny = 70, 40
+    rho, kappa, c = layered_material(nx, ny, 105)
+    dt = 0.4 * hw.cfl_bound("acoustic2d", 4) / c
+    f = {k: v * 1e-3 for k, v in acoustic_fields(nx, ny, 106, "f16").items()}
+    g, gc, _ = gpu_acoustic(nx, ny, 4, "f16", "twosum", dt, rho, kappa, f, 30,
+                            scale_log2=10)
+    fs = {k: v * 1024.0 for k, v in f.items()}
+    w, wc, _ = oracle_acoustic(nx, ny, 4, "f16", "twosum", dt, rho, kappa, fs, 30)
+    assert_bitexact(g, {k: v / 1024.0 for k, v in w.items()}, "scaled")
+    assert_bitexact(gc, {k: v / 1024.0 for k, v in wc.items()}, "scaled comps")
+
+
+def test_sampled_one_step_at_full_size():
+    """4096x4096 layered workload, order 4, fp16+TwoSum in the benchmark's
+    tile shape: after 200 steps, one more step is checked cell by cell against
+    the oracle on local periodic patches around sampled cells (each output
+    cell of one step depends only on a 7x7 neighbourhood)."""
+    w = workloads.layered2d(nsteps=200)
+    pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, 4, "f16", "twosum", w.dx,
+                    w.dt, 0, 4)
+    plan = hw.Plan(pb)
+    plan.set_material([w.rho, w.kappa])
+    plan.set_fields(w.fields())
+    plan.advance(w.nsteps)
+    before, cb = plan.get_fields(comps=True)
+    plan.advance(1)
+    after, ca = plan.get_fields(comps=True)
+    plan.close()
+    rng = np.random.default_rng(7)
+    pts = [(0, 0), (w.ny - 1, w.nx - 1), (0, w.nx - 1)] + \
+        [tuple(rng.integers(0, [w.ny, w.nx])) for _ in range(40)]
+    m = 8
+    for (j, i) in pts:
+        rows = np.arange(j - m, j + m + 1) % w.ny
+        cols = np.arange(i - m, i + m + 1) % w.nx
+        sub = np.ix_(rows, cols)
+        f = {k: before[k][sub] for k in before}
+        c = {k: cb[k][sub] for k in cb}
+        o, oc, _ = oracle.acoustic2d(2 * m + 1, 2 * m + 1, 4, w.dx, w.dt,
+                                     w.rho[sub], w.kappa[sub], f,
+                                     storage="f16", stencil="f32",
+                                     comp="twosum", comps=c, nsteps=1)
+        for k in after:
+            assert after[k][j, i] == o[k][m, m], (k, j, i)
+            assert ca[k][j, i] == oc[k][m, m], (k, j, i)
+
+
+def test_overflow_is_reported():
+    """A state at the top of the fp16 range (Table 1) overflows in one step;
+    the energy becomes non-finite and the sticky status reports it."""
+    nx = ny = 32
+    rho = np.ones((ny, nx))
+    p = np.full((ny, nx), 65504.0)
+    p[16, 16] = -65504.0
+    pb = hw.Problem("acoustic2d", nx, ny, 1, 2, "f16", "none", 1.0, 0.5, 0, 8)
+    plan = hw.Plan(pb)
+    plan.set_material([rho, rho])
+    plan.set_fields({"p": p})
+    plan.advance(2, energy_every=1)
+    with pytest.raises(hw.HalfwaveError) as ei:
+        plan.energy_trace()
+    assert ei.value.name == "HW_E_NONFINITE"
+    e, _ = plan.energy_trace(allow_nonfinite=True)
+    assert np.isfinite(e[0]) and not np.isfinite(e[-1])
+    plan.close()
