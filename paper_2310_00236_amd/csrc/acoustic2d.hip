@@ -44,152 +44,213 @@ __device__ __forceinline__ int find_shot(const A &a, int32_t t)
     return lo;
 }
 
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Periodic wrap of a 32-bit index (any offset).
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
 template <class S, int COMP, int ORDER, int TX, int TY>
 __global__ __launch_bounds__(kThreads) void ac2d_step_kernel(const Ac2dBatch a)
 {
     using T = typename S::store_t;
-    constexpr int R = ORDER / 2;          // velocity halo
-    constexpr int H = 2 * R - 1;          // pressure halo
-    constexpr int PW = TX + 2 * H;        // LDS pressure tile
-    constexpr int PH = TY + 2 * H;
-    constexpr int VXW = TX + 2 * R - 1;   // new vx per row (lx in [-R, TX+R-1))
-    constexpr int VYH = TY + 2 * R - 1;   // new vy rows    (ly in [-R, TY+R-1))
-    __shared__ float ps[PH * PW];
-    __shared__ float vxs[TY * VXW];
-    __shared__ float vys[VYH * TX];
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
+    constexpr int R = ORDER / 2;              // velocity halo
+    constexpr int H = 2 * R - 1;              // pressure halo
+    constexpr int PW = TX + 2 * H, PH = TY + 2 * H, NPT = PW * PH;
+    constexpr int BW = TX + 2 * R, BH = TY + 2 * R, NBT = BW * BH;
+    constexpr int VXW = TX + 2 * R - 1, NVX = TY * VXW;   // lx in [-R, TX+R-1)
+    constexpr int VYH = TY + 2 * R - 1, NVY = VYH * TX;   // ly in [-R, TY+R-1)
+    constexpr int NC = TX * TY;
+    constexpr int KP = cdiv(NPT, kThreads), KB = cdiv(NBT, kThreads);
+    constexpr int KVX = cdiv(NVX, kThreads), KVY = cdiv(NVY, kThreads);
+    constexpr int KC = cdiv(NC, kThreads);
+    __shared__ float ps[NPT];     // old p,   x in [x0-H, x0+TX+H), y likewise
+    __shared__ float bs[NBT];     // 1/rho,   x in [x0-R, x0+TX+R), y likewise
+    __shared__ float vxs[NVX];    // new vx on the tile rows
+    __shared__ float vys[NVY];    // new vy on the tile columns
+    const int tid = threadIdx.x;
 
     int32_t tile = xcd_tile(blockIdx.x, a.total_tiles);
     const int shot = find_shot(a, tile);
     const Ac2dDesc &d = *a.desc[shot];
     const int par = a.parity[shot];
     tile -= a.tile_start[shot];
-    const int64_t nx = d.nx, ny = d.ny, pitch = d.pitch;
-    const int32_t ntx = a.tiles_x[shot];
-    const int64_t x0 = (int64_t)(tile % ntx) * TX;
-    const int64_t y0 = (int64_t)(tile / ntx) * TY;
+    const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
+    const int ntx = a.tiles_x[shot];
+    const int x0 = (tile % ntx) * TX;
+    const int y0 = (tile / ntx) * TY;
     const float w1 = d.w1, w2 = d.w2;
-    const float *__restrict__ b = d.b;
-    const float *__restrict__ kap = d.k;
-    const T *__restrict__ p_in = (const T *)d.p[par];
-    const T *__restrict__ vx_in = (const T *)d.vx[par];
-    const T *__restrict__ vy_in = (const T *)d.vy[par];
-    const T *__restrict__ cvx_in = (const T *)d.cvx[par];
-    const T *__restrict__ cvy_in = (const T *)d.cvy[par];
-    T *__restrict__ p_out = (T *)d.p[par ^ 1];
-    T *__restrict__ vx_out = (T *)d.vx[par ^ 1];
-    T *__restrict__ vy_out = (T *)d.vy[par ^ 1];
-    T *__restrict__ cvx_out = (T *)d.cvx[par ^ 1];
-    T *__restrict__ cvy_out = (T *)d.cvy[par ^ 1];
-    T *__restrict__ cp = (T *)d.cp;
-
-    // 1. old pressure with halo H
+    const float HW_GLOBAL *__restrict__ b = gmem(d.b);
+    const float HW_GLOBAL *__restrict__ kap = gmem(d.k);
+    const W HW_GLOBAL *__restrict__ p_in = gmem((const W *)d.p[par]);
+    const W HW_GLOBAL *__restrict__ vx_in = gmem((const W *)d.vx[par]);
+    const W HW_GLOBAL *__restrict__ vy_in = gmem((const W *)d.vy[par]);
+    W HW_GLOBAL *__restrict__ p_out = gmem((W *)d.p[par ^ 1]);
+    W HW_GLOBAL *__restrict__ vx_out = gmem((W *)d.vx[par ^ 1]);
+    W HW_GLOBAL *__restrict__ vy_out = gmem((W *)d.vy[par ^ 1]);
+    // No index of this tile (halos included) leaves the grid: no wrapping.
     const bool interior = x0 >= H && x0 + TX + H <= nx && y0 >= H &&
                           y0 + TY + H <= ny;
-    for (int idx = threadIdx.x; idx < PH * PW; idx += kThreads) {
-        const int ly = idx / PW, lx = idx % PW;
-        int64_t gy = y0 + ly - H, gx = x0 + lx - H;
-        if (!interior) {
-            gy = wrapn(gy, ny);
-            gx = wrapn(gx, nx);
+
+    // ---- 1. issue every global load of the tile before using any of them
+    float pr[KP], br[KB], kr[KC];
+    W vxo[KVX], vyo[KVY], po[KC];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int e = tid + k * kThreads;
+        if (e < NPT) {
+            int gy = y0 + e / PW - H, gx = x0 + e % PW - H;
+            if (!interior) {
+                gy = wrapi(gy, ny);
+                gx = wrapi(gx, nx);
+            }
+            pr[k] = S::load(WD::v(p_in[gy * pitch + gx]));
         }
-        ps[idx] = S::load(p_in[gy * pitch + gx]);
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int e = tid + k * kThreads;
+        if (e < NBT) {
+            int gy = y0 + e / BW - R, gx = x0 + e % BW - R;
+            if (!interior) {
+                gy = wrapi(gy, ny);
+                gx = wrapi(gx, nx);
+            }
+            br[k] = b[gy * pitch + gx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KVX; ++k) {
+        const int e = tid + k * kThreads;
+        const int gy = y0 + e / VXW;
+        if (e < NVX && gy < ny) {
+            int gx = x0 + e % VXW - R;
+            if (!interior)
+                gx = wrapi(gx, nx);
+            vxo[k] = vx_in[gy * pitch + gx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KVY; ++k) {
+        const int e = tid + k * kThreads;
+        const int gx = x0 + e % TX;
+        if (e < NVY && gx < nx) {
+            int gy = y0 + e / TX - R;
+            if (!interior)
+                gy = wrapi(gy, ny);
+            vyo[k] = vy_in[gy * pitch + gx];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int e = tid + k * kThreads;
+        const int gx = x0 + e % TX, gy = y0 + e / TX;
+        if (e < NC && gx < nx && gy < ny) {
+            const int q = gy * pitch + gx;
+            kr[k] = kap[q];
+            po[k] = p_in[q];
+        }
+    }
+
+    // ---- 2. stage old pressure and buoyancy in LDS
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const int e = tid + k * kThreads;
+        if (e < NPT)
+            ps[e] = pr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int e = tid + k * kThreads;
+        if (e < NBT)
+            bs[e] = br[k];
     }
     __syncthreads();
 
-    // 2a. new vx on the tile rows, x in [x0-R, x0+TX+R-1)
-    for (int idx = threadIdx.x; idx < TY * VXW; idx += kThreads) {
-        const int ly = idx / VXW, lxv = idx % VXW;
-        const int lx = lxv - R;
-        const int64_t gy = y0 + ly;
-        if (gy >= ny)
-            continue;
-        const int64_t gx = wrapn(x0 + lx, nx);
-        const int64_t gx1 = wrap1(gx + 1, nx);
-        const float *pr = &ps[(ly + H) * PW + (lx + H)];
-        const float a0 = pr[1] - pr[0];
-        float g;
-        if constexpr (ORDER == 4) {
-            const float a1 = pr[2] - pr[-1];
-            g = w1 * a0 + w2 * a1;
-        } else {
-            g = w1 * a0;
-        }
-        const int64_t q = gy * pitch + gx;
-        const float bx = 0.5f * (b[q] + b[gy * pitch + gx1]);
-        const float inc = bx * g;
-        float v = S::load(vx_in[q]);
-        float c = COMP ? S::load(cvx_in[q]) : 0.0f;
-        update<S, COMP>(v, c, inc);
-        vxs[idx] = v;
-        if (lx >= 0 && lx < TX && x0 + lx < nx) {
-            vx_out[q] = S::store(v);
-            if (COMP)
-                cvx_out[q] = S::store(c);
+    // ---- 3a. new vx on the tile rows, x in [x0-R, x0+TX+R-1)
+#pragma unroll
+    for (int k = 0; k < KVX; ++k) {
+        const int e = tid + k * kThreads;
+        const int ly = e / VXW, lx = e % VXW - R;
+        if (e < NVX && y0 + ly < ny) {
+            const float *pp = &ps[(ly + H) * PW + (lx + H)];
+            const float a0 = pp[1] - pp[0];
+            float g;
+            if constexpr (ORDER == 4) {
+                const float a1 = pp[2] - pp[-1];
+                g = w1 * a0 + w2 * a1;
+            } else {
+                g = w1 * a0;
+            }
+            const float *bb = &bs[(ly + R) * BW + (lx + R)];
+            const float bx = 0.5f * (bb[0] + bb[1]);
+            const float inc = bx * g;
+            T v = WD::v(vxo[k]), c = WD::c(vxo[k]);
+            update_store<S, COMP>(v, c, inc);
+            vxs[e] = S::load(v);
+            if (lx >= 0 && lx < TX && x0 + lx < nx)
+                vx_out[(y0 + ly) * pitch + x0 + lx] = WD::make(v, c);
         }
     }
 
-    // 2b. new vy on the tile columns, y in [y0-R, y0+TY+R-1)
-    for (int idx = threadIdx.x; idx < VYH * TX; idx += kThreads) {
-        const int lyv = idx / TX, lx = idx % TX;
-        const int ly = lyv - R;
-        const int64_t gx = x0 + lx;
-        if (gx >= nx)
-            continue;
-        const int64_t gy = wrapn(y0 + ly, ny);
-        const int64_t gy1 = wrap1(gy + 1, ny);
-        const float *pc = &ps[(ly + H) * PW + (lx + H)];
-        const float a0 = pc[PW] - pc[0];
-        float g;
-        if constexpr (ORDER == 4) {
-            const float a1 = pc[2 * PW] - pc[-PW];
-            g = w1 * a0 + w2 * a1;
-        } else {
-            g = w1 * a0;
-        }
-        const int64_t q = gy * pitch + gx;
-        const float by = 0.5f * (b[q] + b[gy1 * pitch + gx]);
-        const float inc = by * g;
-        float v = S::load(vy_in[q]);
-        float c = COMP ? S::load(cvy_in[q]) : 0.0f;
-        update<S, COMP>(v, c, inc);
-        vys[idx] = v;
-        if (ly >= 0 && ly < TY && y0 + ly < ny) {
-            vy_out[q] = S::store(v);
-            if (COMP)
-                cvy_out[q] = S::store(c);
+    // ---- 3b. new vy on the tile columns, y in [y0-R, y0+TY+R-1)
+#pragma unroll
+    for (int k = 0; k < KVY; ++k) {
+        const int e = tid + k * kThreads;
+        const int ly = e / TX - R, lx = e % TX;
+        if (e < NVY && x0 + lx < nx) {
+            const float *pp = &ps[(ly + H) * PW + (lx + H)];
+            const float a0 = pp[PW] - pp[0];
+            float g;
+            if constexpr (ORDER == 4) {
+                const float a1 = pp[2 * PW] - pp[-PW];
+                g = w1 * a0 + w2 * a1;
+            } else {
+                g = w1 * a0;
+            }
+            const float *bb = &bs[(ly + R) * BW + (lx + R)];
+            const float by = 0.5f * (bb[0] + bb[BW]);
+            const float inc = by * g;
+            T v = WD::v(vyo[k]), c = WD::c(vyo[k]);
+            update_store<S, COMP>(v, c, inc);
+            vys[e] = S::load(v);
+            if (ly >= 0 && ly < TY && y0 + ly < ny)
+                vy_out[(y0 + ly) * pitch + x0 + lx] = WD::make(v, c);
         }
     }
     __syncthreads();
 
-    // 3. new pressure on the tile
-    for (int idx = threadIdx.x; idx < TY * TX; idx += kThreads) {
-        const int ly = idx / TX, lx = idx % TX;
-        const int64_t gx = x0 + lx, gy = y0 + ly;
-        if (gx >= nx || gy >= ny)
-            continue;
-        const float *vr = &vxs[ly * VXW + lx + R];
-        const float *vc = &vys[(ly + R) * TX + lx];
-        const float ax0 = vr[0] - vr[-1];
-        const float ay0 = vc[0] - vc[-TX];
-        float gxv, gyv;
-        if constexpr (ORDER == 4) {
-            const float ax1 = vr[1] - vr[-2];
-            const float ay1 = vc[TX] - vc[-2 * TX];
-            gxv = w1 * ax0 + w2 * ax1;
-            gyv = w1 * ay0 + w2 * ay1;
-        } else {
-            gxv = w1 * ax0;
-            gyv = w1 * ay0;
+    // ---- 4. new pressure on the tile
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int e = tid + k * kThreads;
+        const int ly = e / TX, lx = e % TX;
+        if (e < NC && x0 + lx < nx && y0 + ly < ny) {
+            const float *vr = &vxs[ly * VXW + lx + R];
+            const float *vc = &vys[(ly + R) * TX + lx];
+            const float ax0 = vr[0] - vr[-1];
+            const float ay0 = vc[0] - vc[-TX];
+            float gxv, gyv;
+            if constexpr (ORDER == 4) {
+                const float ax1 = vr[1] - vr[-2];
+                const float ay1 = vc[TX] - vc[-2 * TX];
+                gxv = w1 * ax0 + w2 * ax1;
+                gyv = w1 * ay0 + w2 * ay1;
+            } else {
+                gxv = w1 * ax0;
+                gyv = w1 * ay0;
+            }
+            const float dv = gxv + gyv;
+            const float inc = kr[k] * dv;
+            T pv = WD::v(po[k]), c = WD::c(po[k]);
+            update_store<S, COMP>(pv, c, inc);
+            p_out[(y0 + ly) * pitch + x0 + lx] = WD::make(pv, c);
         }
-        const float dv = gxv + gyv;
-        const int64_t q = gy * pitch + gx;
-        const float inc = kap[q] * dv;
-        float pv = ps[(ly + H) * PW + (lx + H)];
-        float c = COMP ? S::load(cp[q]) : 0.0f;
-        update<S, COMP>(pv, c, inc);
-        p_out[q] = S::store(pv);
-        if (COMP)
-            cp[q] = S::store(c);
     }
 }
 
@@ -211,7 +272,7 @@ __device__ __forceinline__ double block_sum(double v, double *red)
 // that depends only on the grid size.
 template <class S, int ORDER>
 __global__ __launch_bounds__(kThreads) void ac2d_energy_kernel(
-    const Ac2dDesc *__restrict__ dd, int par, double *__restrict__ partial)
+    const Ac2dDesc *__restrict__ dd, int par, int st, double *__restrict__ partial)
 {
     using T = typename S::store_t;
     __shared__ double red[kThreads];
@@ -221,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void ac2d_energy_kernel(
     const int64_t j1 = wrap1(j + 1, ny);
     const int64_t j2 = wrapn(j + 2, ny);
     const int64_t jm = wrap1(j - 1, ny);
-    const T *__restrict__ p = (const T *)d.p[par];
+    const T *__restrict__ p = (const T *)d.p[par];   // element stride st
     const T *__restrict__ vx = (const T *)d.vx[par];
     const T *__restrict__ vy = (const T *)d.vy[par];
     const double w1 = d.w1, w2 = d.w2;
@@ -229,21 +290,21 @@ __global__ __launch_bounds__(kThreads) void ac2d_energy_kernel(
     for (int64_t i = threadIdx.x; i < nx; i += kThreads) {
         const int64_t i1 = wrap1(i + 1, nx);
         const int64_t q = j * pitch + i;
-        const double pc = S::load(p[q]);
-        double gx = w1 * ((double)S::load(p[j * pitch + i1]) - pc);
-        double gy = w1 * ((double)S::load(p[j1 * pitch + i]) - pc);
+        const double pc = S::load(p[(q) * st]);
+        double gx = w1 * ((double)S::load(p[(j * pitch + i1) * st]) - pc);
+        double gy = w1 * ((double)S::load(p[(j1 * pitch + i) * st]) - pc);
         if constexpr (ORDER == 4) {
             const int64_t i2 = wrapn(i + 2, nx), im = wrap1(i - 1, nx);
-            gx = gx + w2 * ((double)S::load(p[j * pitch + i2]) -
-                            (double)S::load(p[j * pitch + im]));
-            gy = gy + w2 * ((double)S::load(p[j2 * pitch + i]) -
-                            (double)S::load(p[jm * pitch + i]));
+            gx = gx + w2 * ((double)S::load(p[(j * pitch + i2) * st]) -
+                            (double)S::load(p[(j * pitch + im) * st]));
+            gy = gy + w2 * ((double)S::load(p[(j2 * pitch + i) * st]) -
+                            (double)S::load(p[(jm * pitch + i) * st]));
         }
         const double bc = d.b[q];
         const double bx = 0.5 * (bc + (double)d.b[j * pitch + i1]);
         const double by = 0.5 * (bc + (double)d.b[j1 * pitch + i]);
-        const double vxm = S::load(vx[q]);
-        const double vym = S::load(vy[q]);
+        const double vxm = S::load(vx[(q) * st]);
+        const double vym = S::load(vy[(q) * st]);
         const double vxp = vxm + bx * gx;
         const double vyp = vym + by * gy;
         double e = (pc * pc) / (double)d.k[q] + (vxm * vxp) / bx;
@@ -329,25 +390,25 @@ hipError_t launch_ac2d_step(const Ac2dBatch &a, int storage, int comp,
 
 template <class S>
 static hipError_t energy_order(const Ac2dDesc *d, int par, int64_t ny,
-                               int order, double *partial, hipStream_t s)
+                               int order, int st, double *partial, hipStream_t s)
 {
     if (order == 4)
         hipLaunchKernelGGL((ac2d_energy_kernel<S, 4>), dim3(ny), dim3(kThreads),
-                           0, s, d, par, partial);
+                           0, s, d, par, st, partial);
     else
         hipLaunchKernelGGL((ac2d_energy_kernel<S, 2>), dim3(ny), dim3(kThreads),
-                           0, s, d, par, partial);
+                           0, s, d, par, st, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity, int64_t ny,
-                              int storage, int order, double *partial,
-                              hipStream_t s)
+                              int storage, int order, int stride,
+                              double *partial, hipStream_t s)
 {
     switch (storage) {
-    case HW_F32: return energy_order<F32>(d_desc, parity, ny, order, partial, s);
-    case HW_F16: return energy_order<F16>(d_desc, parity, ny, order, partial, s);
-    case HW_BF16: return energy_order<BF16>(d_desc, parity, ny, order, partial, s);
+    case HW_F32: return energy_order<F32>(d_desc, parity, ny, order, stride, partial, s);
+    case HW_F16: return energy_order<F16>(d_desc, parity, ny, order, stride, partial, s);
+    case HW_BF16: return energy_order<BF16>(d_desc, parity, ny, order, stride, partial, s);
     }
     return hipErrorInvalidValue;
 }

@@ -61,26 +61,28 @@ __device__ __forceinline__ uint16_t from_double<BF16>(double x)
 template <class S>
 __global__ __launch_bounds__(kThreads) void to_storage_kernel(
     const double *__restrict__ src, typename S::store_t *__restrict__ dst,
-    int64_t nx, int64_t rows, int64_t pitch, double scale)
+    int64_t nx, int64_t rows, int64_t pitch, int stride, int offset,
+    double scale)
 {
     const int64_t n = nx * rows;
     for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * kThreads) {
         const int64_t r = t / nx, i = t % nx;
-        dst[r * pitch + i] = from_double<S>(src[t] * scale);
+        dst[(r * pitch + i) * stride + offset] = from_double<S>(src[t] * scale);
     }
 }
 
 template <class S>
 __global__ __launch_bounds__(kThreads) void from_storage_kernel(
     const typename S::store_t *__restrict__ src, double *__restrict__ dst,
-    int64_t nx, int64_t rows, int64_t pitch, double scale)
+    int64_t nx, int64_t rows, int64_t pitch, int stride, int offset,
+    double scale)
 {
     const int64_t n = nx * rows;
     for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * kThreads) {
         const int64_t r = t / nx, i = t % nx;
-        dst[t] = (double)S::load(src[r * pitch + i]) * scale;
+        dst[t] = (double)S::load(src[(r * pitch + i) * stride + offset]) * scale;
     }
 }
 
@@ -119,21 +121,22 @@ static dim3 grid_for(int64_t n)
 
 hipError_t launch_to_storage(const double *src, void *dst, int storage,
                              int64_t nx, int64_t rows, int64_t pitch,
-                             double scale, hipStream_t s)
+                             int stride, int offset, double scale,
+                             hipStream_t s)
 {
     const dim3 g = grid_for(nx * rows), b(kThreads);
     switch (storage) {
     case HW_F32:
         hipLaunchKernelGGL(to_storage_kernel<F32>, g, b, 0, s, src,
-                           (float *)dst, nx, rows, pitch, scale);
+                           (float *)dst, nx, rows, pitch, stride, offset, scale);
         break;
     case HW_F16:
         hipLaunchKernelGGL(to_storage_kernel<F16>, g, b, 0, s, src,
-                           (_Float16 *)dst, nx, rows, pitch, scale);
+                           (_Float16 *)dst, nx, rows, pitch, stride, offset, scale);
         break;
     case HW_BF16:
         hipLaunchKernelGGL(to_storage_kernel<BF16>, g, b, 0, s, src,
-                           (uint16_t *)dst, nx, rows, pitch, scale);
+                           (uint16_t *)dst, nx, rows, pitch, stride, offset, scale);
         break;
     default:
         return hipErrorInvalidValue;
@@ -143,21 +146,22 @@ hipError_t launch_to_storage(const double *src, void *dst, int storage,
 
 hipError_t launch_from_storage(const void *src, double *dst, int storage,
                                int64_t nx, int64_t rows, int64_t pitch,
-                               double scale, hipStream_t s)
+                               int stride, int offset, double scale,
+                               hipStream_t s)
 {
     const dim3 g = grid_for(nx * rows), b(kThreads);
     switch (storage) {
     case HW_F32:
         hipLaunchKernelGGL(from_storage_kernel<F32>, g, b, 0, s,
-                           (const float *)src, dst, nx, rows, pitch, scale);
+                           (const float *)src, dst, nx, rows, pitch, stride, offset, scale);
         break;
     case HW_F16:
         hipLaunchKernelGGL(from_storage_kernel<F16>, g, b, 0, s,
-                           (const _Float16 *)src, dst, nx, rows, pitch, scale);
+                           (const _Float16 *)src, dst, nx, rows, pitch, stride, offset, scale);
         break;
     case HW_BF16:
         hipLaunchKernelGGL(from_storage_kernel<BF16>, g, b, 0, s,
-                           (const uint16_t *)src, dst, nx, rows, pitch, scale);
+                           (const uint16_t *)src, dst, nx, rows, pitch, stride, offset, scale);
         break;
     default:
         return hipErrorInvalidValue;

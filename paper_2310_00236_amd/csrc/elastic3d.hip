@@ -35,9 +35,14 @@ __device__ __forceinline__ int find_shot3(const El3dBatch &a, int32_t t)
 }
 
 struct Cell {
-    int64_t i, j, k;
+    int i, j, k;
     bool valid;
 };
+
+__device__ __forceinline__ int wrapu(int i, int n)
+{
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
 
 template <int TX, int TY>
 __device__ __forceinline__ Cell locate(const El3dBatch &a, const El3dDesc *&dp)
@@ -47,40 +52,42 @@ __device__ __forceinline__ Cell locate(const El3dBatch &a, const El3dDesc *&dp)
     dp = a.desc[shot];
     const El3dDesc &d = *dp;
     tile -= a.tile_start[shot];
-    const int32_t ntx = a.tiles_x[shot];
-    const int32_t per_slice = ntx * a.tiles_y[shot];
-    const int64_t k = tile / per_slice;
-    const int32_t r = tile % per_slice;
+    const int ntx = a.tiles_x[shot];
+    const int per_slice = ntx * a.tiles_y[shot];
+    const int r = tile % per_slice;
     Cell c;
-    c.i = (int64_t)(r % ntx) * TX + threadIdx.x % TX;
-    c.j = (int64_t)(r / ntx) * TY + threadIdx.x / TX;
-    c.k = k;
-    c.valid = c.i < d.nx && c.j < d.ny;
+    c.k = tile / per_slice;
+    c.i = (r % ntx) * TX + (int)threadIdx.x % TX;
+    c.j = (r / ntx) * TY + (int)threadIdx.x / TX;
+    c.valid = c.i < (int)d.nx && c.j < (int)d.ny;
     return c;
 }
 
 template <class S, int COMP, int TX, int TY>
 __global__ __launch_bounds__(kThreads) void el3d_velocity_kernel(const El3dBatch a)
 {
-    using T = typename S::store_t;
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
     const El3dDesc *dp;
     const Cell cl = locate<TX, TY>(a, dp);
     if (!cl.valid)
         return;
     const El3dDesc &d = *dp;
-    const int64_t nx = d.nx, ny = d.ny, nz = d.nz, pitch = d.pitch, slab = d.slab;
-    const int64_t i = cl.i, j = cl.j, k = cl.k;
-    const int64_t ip = wrap1(i + 1, nx), im = wrap1(i - 1, nx);
-    const int64_t jp = wrap1(j + 1, ny), jm = wrap1(j - 1, ny);
-    const int64_t kp = wrap1(k + 1, nz), km = wrap1(k - 1, nz);
-    const int64_t row = k * slab + j * pitch;
-    const int64_t q = row + i;
+    const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
+    const int pitch = (int)d.pitch, slab = (int)d.slab;
+    const int i = cl.i, j = cl.j, k = cl.k;
+    const int ip = wrapu(i + 1, nx), im = wrapu(i - 1, nx);
+    const int jp = wrapu(j + 1, ny), jm = wrapu(j - 1, ny);
+    const int kp = wrapu(k + 1, nz), km = wrapu(k - 1, nz);
+    const int row = k * slab + j * pitch;
+    const int q = row + i;
     const float w = d.w;
-    const float *__restrict__ B = d.b;
-    const T *sxx = (const T *)d.f[3], *syy = (const T *)d.f[4];
-    const T *szz = (const T *)d.f[5], *sxy = (const T *)d.f[6];
-    const T *sxz = (const T *)d.f[7], *syz = (const T *)d.f[8];
-    auto L = [](const T *p, int64_t idx) { return S::load(p[idx]); };
+    using GW = const W HW_GLOBAL *;
+    const float HW_GLOBAL *__restrict__ B = gmem(d.b);
+    GW sxx = gmem((const W *)d.f[3]), syy = gmem((const W *)d.f[4]);
+    GW szz = gmem((const W *)d.f[5]), sxy = gmem((const W *)d.f[6]);
+    GW sxz = gmem((const W *)d.f[7]), syz = gmem((const W *)d.f[8]);
+    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
     const float sxy_q = L(sxy, q), sxz_q = L(sxz, q), syz_q = L(syz, q);
     const float bq = B[q];
     float inc[3];
@@ -110,52 +117,53 @@ __global__ __launch_bounds__(kThreads) void el3d_velocity_kernel(const El3dBatch
     }
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        T *vf = (T *)d.f[f];
-        T *cf = (T *)d.c[f];
-        float v = S::load(vf[q]);
-        float c = COMP ? S::load(cf[q]) : 0.0f;
-        update<S, COMP>(v, c, inc[f]);
-        vf[q] = S::store(v);
-        if (COMP)
-            cf[q] = S::store(c);
+        W HW_GLOBAL *vf = gmem((W *)d.f[f]);
+        const W old = vf[q];
+        auto v = WD::v(old), c = WD::c(old);
+        update_store<S, COMP>(v, c, inc[f]);
+        vf[q] = WD::make(v, c);
     }
 }
 
 template <class S, int COMP, int TX, int TY>
 __global__ __launch_bounds__(kThreads) void el3d_stress_kernel(const El3dBatch a)
 {
-    using T = typename S::store_t;
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
     const El3dDesc *dp;
     const Cell cl = locate<TX, TY>(a, dp);
     if (!cl.valid)
         return;
     const El3dDesc &d = *dp;
-    const int64_t nx = d.nx, ny = d.ny, nz = d.nz, pitch = d.pitch, slab = d.slab;
-    const int64_t i = cl.i, j = cl.j, k = cl.k;
-    const int64_t ip = wrap1(i + 1, nx), im = wrap1(i - 1, nx);
-    const int64_t jp = wrap1(j + 1, ny), jm = wrap1(j - 1, ny);
-    const int64_t kp = wrap1(k + 1, nz), km = wrap1(k - 1, nz);
-    const int64_t row = k * slab + j * pitch;
-    const int64_t q = row + i;
+    const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
+    const int pitch = (int)d.pitch, slab = (int)d.slab;
+    const int i = cl.i, j = cl.j, k = cl.k;
+    const int ip = wrapu(i + 1, nx), im = wrapu(i - 1, nx);
+    const int jp = wrapu(j + 1, ny), jm = wrapu(j - 1, ny);
+    const int kp = wrapu(k + 1, nz), km = wrapu(k - 1, nz);
+    const int row = k * slab + j * pitch;
+    const int q = row + i;
     const float w = d.w;
-    const T *vx = (const T *)d.f[0], *vy = (const T *)d.f[1];
-    const T *vz = (const T *)d.f[2];
-    auto L = [](const T *p, int64_t idx) { return S::load(p[idx]); };
-    const float *__restrict__ M = d.mu;
+    using GW = const W HW_GLOBAL *;
+    GW vx = gmem((const W *)d.f[0]), vy = gmem((const W *)d.f[1]);
+    GW vz = gmem((const W *)d.f[2]);
+    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
+    const float HW_GLOBAL *__restrict__ M = gmem(d.mu);
+    const float HW_GLOBAL *__restrict__ LM = gmem(d.lam);
     const float vx_q = L(vx, q), vy_q = L(vy, q), vz_q = L(vz, q);
     const float ex = w * (vx_q - L(vx, row + im));
     const float ey = w * (vy_q - L(vy, k * slab + jm * pitch + i));
     const float ez = w * (vz_q - L(vz, km * slab + j * pitch + i));
-    const float lam = d.lam[q];
+    const float lam = LM[q];
     const float mq = M[q];
     const float l2m = lam + 2.0f * mq;
     float inc[6];
     inc[0] = l2m * ex + lam * (ey + ez);
     inc[1] = l2m * ey + lam * (ex + ez);
     inc[2] = l2m * ez + lam * (ex + ey);
-    const int64_t q_ip = row + ip;
-    const int64_t q_jp = k * slab + jp * pitch + i;
-    const int64_t q_kp = kp * slab + j * pitch + i;
+    const int q_ip = row + ip;
+    const int q_jp = k * slab + jp * pitch + i;
+    const int q_kp = kp * slab + j * pitch + i;
     {   // sxy at (i+1/2, j+1/2, k)
         const float a1 = L(vy, q_ip) - vy_q;
         const float a2 = L(vx, q_jp) - vx_q;
@@ -182,14 +190,11 @@ __global__ __launch_bounds__(kThreads) void el3d_stress_kernel(const El3dBatch a
     }
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-        T *sf = (T *)d.f[3 + f];
-        T *cf = (T *)d.c[3 + f];
-        float v = S::load(sf[q]);
-        float c = COMP ? S::load(cf[q]) : 0.0f;
-        update<S, COMP>(v, c, inc[f]);
-        sf[q] = S::store(v);
-        if (COMP)
-            cf[q] = S::store(c);
+        W HW_GLOBAL *sf = gmem((W *)d.f[3 + f]);
+        const W old = sf[q];
+        auto v = WD::v(old), c = WD::c(old);
+        update_store<S, COMP>(v, c, inc[f]);
+        sf[q] = WD::make(v, c);
     }
 }
 
@@ -208,7 +213,7 @@ __device__ __forceinline__ double block_sum3(double v, double *red)
 // Energy of the elastic state, one workgroup per (j, k) row, fp64.
 template <class S>
 __global__ __launch_bounds__(kThreads) void el3d_energy_kernel(
-    const El3dDesc *__restrict__ dd, double *__restrict__ partial)
+    const El3dDesc *__restrict__ dd, int st, double *__restrict__ partial)
 {
     using T = typename S::store_t;
     __shared__ double red[kThreads];
@@ -222,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void el3d_energy_kernel(
     const T *f[9];
     for (int n = 0; n < 9; ++n)
         f[n] = (const T *)d.f[n];
-    auto L = [&](int n, int64_t idx) { return (double)S::load(f[n][idx]); };
+    auto L = [&](int n, int64_t idx) { return (double)S::load(f[n][idx * st]); };
     const float *B = d.b, *LM = d.lam, *M = d.mu;
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < nx; i += kThreads) {
@@ -322,20 +327,21 @@ hipError_t launch_el3d_step(const El3dBatch &a, int storage, int comp,
 }
 
 hipError_t launch_el3d_energy(const El3dDesc *d_desc, int64_t rows,
-                              int storage, double *partial, hipStream_t s)
+                              int storage, int stride, double *partial,
+                              hipStream_t s)
 {
     switch (storage) {
     case HW_F32:
         hipLaunchKernelGGL(el3d_energy_kernel<F32>, dim3(rows), dim3(kThreads),
-                           0, s, d_desc, partial);
+                           0, s, d_desc, stride, partial);
         break;
     case HW_F16:
         hipLaunchKernelGGL(el3d_energy_kernel<F16>, dim3(rows), dim3(kThreads),
-                           0, s, d_desc, partial);
+                           0, s, d_desc, stride, partial);
         break;
     case HW_BF16:
         hipLaunchKernelGGL(el3d_energy_kernel<BF16>, dim3(rows), dim3(kThreads),
-                           0, s, d_desc, partial);
+                           0, s, d_desc, stride, partial);
         break;
     default:
         return hipErrorInvalidValue;

@@ -112,6 +112,80 @@ __device__ __forceinline__ void update(float &v, float &c, float inc)
     }
 }
 
+// The same updates on values held in the storage type.  For fp16 the
+// compensated sum runs on native half-precision instructions: each of its
+// operations has fp16 operands, so the half-precision instruction's result
+// is the correctly rounded fp16 result the definition asks for.  Only the
+// narrowing of the fp32 increment goes through an explicit rounding.
+template <class S, int COMP>
+__device__ __forceinline__ void update_store(typename S::store_t &v,
+                                             typename S::store_t &c, float inc)
+{
+    if constexpr (S::id == F16::id) {
+        if constexpr (COMP == COMP_NONE) {
+            const _Float16 r = (_Float16)opaque(inc);
+            v = v + r;
+        } else {
+            const _Float16 y = (_Float16)opaque(inc + (float)c);
+            const _Float16 s = v + y;
+            if constexpr (COMP == COMP_FAST2SUM) {
+                const _Float16 z = s - v;
+                c = y - z;
+            } else {
+                const _Float16 pa = s - y;
+                const _Float16 pb = s - pa;
+                const _Float16 da = v - pa;
+                const _Float16 db = y - pb;
+                c = da + db;
+            }
+            v = s;
+        }
+    } else {
+        float vf = S::load(v), cf = COMP ? S::load(c) : 0.0f;
+        update<S, COMP>(vf, cf, inc);
+        v = S::store(vf);
+        if (COMP)
+            c = S::store(cf);
+    }
+}
+
+// Memory word of one field at one cell: the value alone, or the value and
+// its compensation term side by side.
+template <class S, int COMP>
+struct Word {
+    using T = typename S::store_t;
+    typedef T type __attribute__((ext_vector_type(2)));   // (value, comp)
+    __device__ __forceinline__ static T v(type w) { return w[0]; }
+    __device__ __forceinline__ static T c(type w) { return w[1]; }
+    __device__ __forceinline__ static type make(T v, T c) { return type{v, c}; }
+};
+
+template <class S>
+struct Word<S, COMP_NONE> {
+    using T = typename S::store_t;
+    using type = T;
+    __device__ __forceinline__ static T v(type w) { return w; }
+    __device__ __forceinline__ static T c(type) { return T(0); }
+    __device__ __forceinline__ static type make(T v, T) { return v; }
+};
+
+// Pointers into device memory in the global address space.  The buffers
+// reach the kernels through descriptors as generic pointers; without the
+// cast every access would be a flat instruction, which the hardware counts
+// against both the vector-memory and the LDS counters, so each wait for an
+// LDS read would also wait for outstanding global stores.
+#define HW_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T HW_GLOBAL *gmem(T *p)
+{
+    return (T HW_GLOBAL *)p;
+}
+template <class T>
+__device__ __forceinline__ const T HW_GLOBAL *gmem(const T *p)
+{
+    return (const T HW_GLOBAL *)p;
+}
+
 // Periodic index for offsets of at most one period beyond [0, n).
 __device__ __forceinline__ int64_t wrap1(int64_t i, int64_t n)
 {

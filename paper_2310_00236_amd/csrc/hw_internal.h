@@ -13,29 +13,26 @@ constexpr int kThreads = 256;     // threads per workgroup (4 wavefronts)
 constexpr int kNumXcd = 8;        // MI355X: 8 accelerator complex dies
 
 // Device-resident description of one 2D acoustic plan.  Buffers are
-// row-major with a padded row pitch (elements).  The velocity fields and
-// their compensation terms ping-pong between two sets so that a tile can
-// recompute its neighbours' new velocities from old values; the pressure
-// compensation is read and written only by the cell's owner and stays in
-// place.
+// row-major with a padded row pitch (elements).  With compensation, every
+// field value is stored next to its compensation term (one word of two
+// storage-format values per cell), so a cell's state of a field is one
+// memory access.  The fields ping-pong between two sets so that a tile can
+// recompute its neighbours' new velocities from old values.
 struct Ac2dDesc {
     int64_t nx, ny, pitch;
     float w1, w2;                 // stencil weights c_k * dt/dx (fp32)
     const float *b;               // 1/rho at p points
     const float *k;               // kappa at p points
-    void *vx[2], *vy[2], *p[2];   // field sets (storage format)
-    void *cvx[2], *cvy[2];        // velocity compensation sets
-    void *cp;                     // pressure compensation (in place)
+    void *vx[2], *vy[2], *p[2];   // field sets (storage words)
 };
 
 // Device-resident description of one 3D elastic plan (updated in place by
-// a velocity pass followed by a stress pass).
+// a velocity pass followed by a stress pass); same word layout.
 struct El3dDesc {
     int64_t nx, ny, nz, pitch, slab;
     float w;                      // dt/dx (fp32)
     const float *b, *lam, *mu;    // at cell centres
     void *f[9];                   // vx vy vz sxx syy szz sxy sxz syz
-    void *c[9];                   // compensation terms (nullptr if none)
 };
 
 // Arguments of one batched launch: the shots it covers, the parity (which
@@ -68,23 +65,27 @@ constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
 hipError_t launch_ac2d_step(const Ac2dBatch &a, int storage, int comp,
                             int order, int tile, hipStream_t s);
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
-                              int64_t ny, int storage, int order,
+                              int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);
 hipError_t launch_el3d_step(const El3dBatch &a, int storage, int comp,
                             int tile, hipStream_t s);
 hipError_t launch_el3d_energy(const El3dDesc *d_desc, int64_t rows,
-                              int storage, double *partial, hipStream_t s);
+                              int storage, int stride, double *partial,
+                              hipStream_t s);
 hipError_t launch_energy_finish(const double *partial, int64_t n,
                                 double factor, double *out, int32_t *flag,
                                 hipStream_t s);
 
-// Conversions between fp64 host-layout arrays and the device layouts.
+// Conversions between fp64 host-layout arrays and the device layouts:
+// storage element (r*pitch + i)*stride + offset holds host value r*nx + i.
 hipError_t launch_to_storage(const double *src, void *dst, int storage,
                              int64_t nx, int64_t rows, int64_t pitch,
-                             double scale, hipStream_t s);
+                             int stride, int offset, double scale,
+                             hipStream_t s);
 hipError_t launch_from_storage(const void *src, double *dst, int storage,
                                int64_t nx, int64_t rows, int64_t pitch,
-                               double scale, hipStream_t s);
+                               int stride, int offset, double scale,
+                               hipStream_t s);
 hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_material(const double *src, float *dst, int reciprocal,
                            int64_t nx, int64_t rows, int64_t pitch,

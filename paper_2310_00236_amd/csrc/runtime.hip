@@ -68,8 +68,9 @@ double cfl_bound(int physics, int order)
 struct Layout {
     int nf = 0, nm = 0, sets = 1;
     int64_t pitch = 0, slab = 0, rows = 0, cells = 0;
+    int words = 1;                 // storage values per cell and field
     size_t field_bytes = 0, mat_bytes = 0;
-    size_t off_fld[2][9] = {}, off_cmp[2][9] = {};
+    size_t off_fld[2][9] = {};
     size_t off_mat[3] = {}, off_staging = 0, off_partial = 0, off_trace = 0;
     size_t off_flags = 0, off_desc = 0, total = 0;
 };
@@ -106,10 +107,12 @@ hw_status validate(const hw_problem *pb)
     const float w = (float)(pb->dt / pb->dx);
     if (!std::isfinite(w) || w == 0.0f)
         return fail(HW_E_INVAL, "dt/dx does not fit fp32");
-    // tile counts must fit the 32-bit launch indexing
-    const double tiles = std::ceil(pb->nx / 32.0) * std::ceil(pb->ny / 1.0) * pb->nz;
-    if (tiles > 2.0e9)
-        return fail(HW_E_INVAL, "grid too large for one launch");
+    // kernels index each array with 32-bit offsets (padded rows)
+    const double padded = std::ceil(pb->nx / (double)kPitchAlign) * kPitchAlign *
+                          (double)pb->ny * (double)pb->nz;
+    if (padded > 2147483647.0)
+        return fail(HW_E_INVAL, "grid too large for 32-bit indexing (padded "
+                                "nx*ny*nz must stay below 2^31)");
     return HW_OK;
 }
 
@@ -124,7 +127,10 @@ Layout make_layout(const hw_problem *pb)
     L.slab = L.pitch * pb->ny;
     L.rows = pb->ny * pb->nz;
     L.cells = pb->nx * pb->ny * pb->nz;
-    L.field_bytes = align_up((size_t)(L.slab * pb->nz) * esize(pb->storage), kAlign);
+    // with compensation each cell holds (value, compensation) side by side
+    L.words = pb->comp != HW_COMP_NONE ? 2 : 1;
+    L.field_bytes = align_up((size_t)(L.slab * pb->nz) * esize(pb->storage) * L.words,
+                             kAlign);
     L.mat_bytes = align_up((size_t)(L.slab * pb->nz) * 4, kAlign);
     size_t off = 0;
     for (int s = 0; s < L.sets; ++s)
@@ -132,18 +138,6 @@ Layout make_layout(const hw_problem *pb)
             L.off_fld[s][f] = off;
             off += L.field_bytes;
         }
-    if (pb->comp != HW_COMP_NONE) {
-        for (int s = 0; s < L.sets; ++s)
-            for (int f = 0; f < L.nf; ++f) {
-                // the 2D pressure compensation is not ping-ponged
-                if (ac && f == 2 && s == 1) {
-                    L.off_cmp[s][f] = L.off_cmp[0][f];
-                    continue;
-                }
-                L.off_cmp[s][f] = off;
-                off += L.field_bytes;
-            }
-    }
     for (int m = 0; m < L.nm; ++m) {
         L.off_mat[m] = off;
         off += L.mat_bytes;
@@ -178,7 +172,6 @@ struct hw_plan {
     Layout L;
     char *arena;
     void *fld[2][9];
-    void *cmp[2][9];
     float *mat[3];
     double *staging, *partial, *trace;
     int32_t *flags;
@@ -280,11 +273,12 @@ hw_status record_energy(hw_plan *p, hipStream_t s)
     double factor = 0.5 * p->pb.dx * p->pb.dx * p->scale_down * p->scale_down;
     if (p->pb.physics == HW_ACOUSTIC2D) {
         e = launch_ac2d_energy((const Ac2dDesc *)p->d_desc, p->cur, p->pb.ny,
-                               p->pb.storage, p->pb.order, p->partial, s);
+                               p->pb.storage, p->pb.order, p->L.words,
+                               p->partial, s);
     } else {
         factor *= p->pb.dx;
         e = launch_el3d_energy((const El3dDesc *)p->d_desc, p->L.rows,
-                               p->pb.storage, p->partial, s);
+                               p->pb.storage, p->L.words, p->partial, s);
     }
     if (e == hipSuccess)
         e = launch_energy_finish(p->partial, p->L.rows, factor,
@@ -489,8 +483,6 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
         for (int f = 0; f < 9; ++f) {
             const int ss = s < L.sets ? s : 0;
             p->fld[s][f] = f < L.nf ? p->arena + L.off_fld[ss][f] : nullptr;
-            p->cmp[s][f] = (f < L.nf && pb->comp != HW_COMP_NONE)
-                               ? p->arena + L.off_cmp[ss][f] : nullptr;
         }
     for (int m = 0; m < 3; ++m)
         p->mat[m] = m < L.nm ? (float *)(p->arena + L.off_mat[m]) : nullptr;
@@ -516,10 +508,7 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
             d.vx[s] = p->fld[s][0];
             d.vy[s] = p->fld[s][1];
             d.p[s] = p->fld[s][2];
-            d.cvx[s] = p->cmp[s][0];
-            d.cvy[s] = p->cmp[s][1];
         }
-        d.cp = p->cmp[0][2];
     } else {
         El3dDesc &d = p->h3;
         std::memset(&d, 0, sizeof(d));
@@ -532,10 +521,8 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
         d.b = p->mat[0];
         d.lam = p->mat[1];
         d.mu = p->mat[2];
-        for (int f = 0; f < 9; ++f) {
+        for (int f = 0; f < 9; ++f)
             d.f[f] = p->fld[0][f];
-            d.c[f] = p->cmp[0][f];
-        }
     }
     *out = p;
     return HW_OK;
@@ -573,19 +560,16 @@ hw_status hw_set_fields(hw_plan *p, const double *const *fields, void *stream)
         return st;
     hipStream_t s = S(stream);
     for (int f = 0; f < p->L.nf; ++f) {
-        if (!fields[f]) {
-            HW_HIP(launch_fill_zero(p->fld[0][f], p->L.field_bytes, s));
+        // zero values and compensation terms, then write the values
+        HW_HIP(launch_fill_zero(p->fld[0][f], p->L.field_bytes, s));
+        if (!fields[f])
             continue;
-        }
         HW_HIP(hipMemcpyAsync(p->staging, fields[f], (size_t)p->L.cells * 8,
                               hipMemcpyHostToDevice, s));
         HW_HIP(launch_to_storage(p->staging, p->fld[0][f], p->pb.storage, p->pb.nx,
-                                 p->L.rows, p->L.pitch, p->scale_up, s));
+                                 p->L.rows, p->L.pitch, p->L.words, 0,
+                                 p->scale_up, s));
     }
-    if (p->pb.comp != HW_COMP_NONE)
-        for (int set = 0; set < p->L.sets; ++set)
-            for (int f = 0; f < p->L.nf; ++f)
-                HW_HIP(launch_fill_zero(p->cmp[set][f], p->L.field_bytes, s));
     HW_HIP(launch_fill_zero(p->flags, kAlign, s));
     if ((st = upload_desc(p, s)) != HW_OK)
         return st;
@@ -664,9 +648,9 @@ hw_status hw_get_fields(hw_plan *p, double *const *fields, double *const *comps,
                 std::memset(dst[f], 0, bytes);
                 continue;
             }
-            const void *src = pass == 0 ? p->fld[p->cur][f] : p->cmp[p->cur][f];
-            HW_HIP(launch_from_storage(src, p->staging, p->pb.storage, p->pb.nx,
-                                       p->L.rows, p->L.pitch, p->scale_down, s));
+            HW_HIP(launch_from_storage(p->fld[p->cur][f], p->staging, p->pb.storage,
+                                       p->pb.nx, p->L.rows, p->L.pitch, p->L.words,
+                                       pass, p->scale_down, s));
             HW_HIP(hipMemcpyAsync(dst[f], p->staging, bytes, hipMemcpyDeviceToHost, s));
         }
     }
@@ -684,8 +668,7 @@ hw_status hw_state_size(const hw_plan *p, size_t *bytes)
 {
     if (!p || !bytes)
         return fail(HW_E_INVAL, "plan or bytes is NULL");
-    const int ncomp = p->pb.comp != HW_COMP_NONE ? p->L.nf : 0;
-    *bytes = sizeof(BlobHeader) + (size_t)(p->L.nf + ncomp) * p->L.field_bytes;
+    *bytes = sizeof(BlobHeader) + (size_t)p->L.nf * p->L.field_bytes;
     return HW_OK;
 }
 
@@ -718,10 +701,6 @@ hw_status hw_state_export(hw_plan *p, void *blob, size_t bytes, void *stream)
     for (int f = 0; f < p->L.nf; ++f, dst += p->L.field_bytes)
         HW_HIP(hipMemcpyAsync(dst, p->fld[p->cur][f], p->L.field_bytes,
                               hipMemcpyDeviceToHost, s));
-    if (p->pb.comp != HW_COMP_NONE)
-        for (int f = 0; f < p->L.nf; ++f, dst += p->L.field_bytes)
-            HW_HIP(hipMemcpyAsync(dst, p->cmp[p->cur][f], p->L.field_bytes,
-                                  hipMemcpyDeviceToHost, s));
     HW_HIP(hipStreamSynchronize(s));
     return HW_OK;
 }
@@ -750,10 +729,6 @@ hw_status hw_state_import(hw_plan *p, const void *blob, size_t bytes, void *stre
     for (int f = 0; f < p->L.nf; ++f, src += p->L.field_bytes)
         HW_HIP(hipMemcpyAsync(p->fld[0][f], src, p->L.field_bytes,
                               hipMemcpyHostToDevice, s));
-    if (p->pb.comp != HW_COMP_NONE)
-        for (int f = 0; f < p->L.nf; ++f, src += p->L.field_bytes)
-            HW_HIP(hipMemcpyAsync(p->cmp[0][f], src, p->L.field_bytes,
-                                  hipMemcpyHostToDevice, s));
     HW_HIP(launch_fill_zero(p->flags, kAlign, s));
     HW_HIP(hipStreamSynchronize(s));
     p->cur = 0;
