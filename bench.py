@@ -138,6 +138,148 @@ def cpu_baseline(w, target_s=15.0):
                       f"workload, fp16+TwoSum emulated, {secs:.1f} s"}
 
 
+ELASTIC_BYTES_ALGO = {"f32+none": 84, "f16+twosum": 84, "f16+none": 48}
+ELASTIC_BYTES_TWO_PASS = {"f32+none": 120, "f16+twosum": 120, "f16+none": 60}
+
+
+def run_elastic(hw, torch, n, steps, warmup, variants):
+    """3D elastic velocity-stress workload: n^3 periodic, smooth random
+    rho/lambda/mu (ratio <= 3), CFL 0.3, explosive Gaussian source on the
+    normal stresses."""
+    import workloads
+    from paper_2310_00236_amd import tuning
+    w = workloads.smooth3d(n, nsteps=steps)
+    every = max(steps // 10, 1)
+    out = {}
+    for storage, comp in variants:
+        key = f"{storage}+{comp}"
+        pb = hw.Problem("elastic3d", n, n, n, 2, storage, comp, w.dx, w.dt, 0,
+                        (steps + warmup) // every + 4)
+        plan = hw.Plan(pb)
+        plan.set_tile(tuning.best_tile("elastic3d", 2, storage, comp, n, n, n))
+        plan.set_material([w.rho, w.lam, w.mu])
+        plan.set_fields(w.fields())
+        stream = torch.cuda.current_stream()
+        plan.record_energy()
+        plan.advance(warmup, every)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        plan.advance(steps, every)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        energy, _ = plan.energy_trace()
+        plan.close()
+        cells = n ** 3
+        step_ms = ms / steps
+        out[key] = {
+            "glups": cells * steps / (ms * 1e-3) / 1e9,
+            "ms_per_step": step_ms,
+            "energy_drift": float(np.max(np.abs(energy - energy[0])) / energy[0]),
+            "bytes_per_cell_step_algorithmic": ELASTIC_BYTES_ALGO[key],
+            "bytes_per_cell_step_two_pass": ELASTIC_BYTES_TWO_PASS[key],
+            "hbm_gbs_algorithmic": ELASTIC_BYTES_ALGO[key] * cells / (step_ms * 1e-3) / 1e9,
+            "hbm_gbs_two_pass": ELASTIC_BYTES_TWO_PASS[key] * cells / (step_ms * 1e-3) / 1e9,
+        }
+        print(f"# elastic3d {n}^3 {key}: {out[key]}", file=sys.stderr, flush=True)
+    return {"workload": f"elastic3d order-2 {n}^3 periodic, smooth random medium, "
+                        f"CFL 0.3, explosive source, {steps} steps",
+            "variants": out,
+            "vs_f32": out["f16+twosum"]["glups"] / out["f32+none"]["glups"]
+            if "f16+twosum" in out and "f32+none" in out else None}
+
+
+def run_batched(hw, torch, nshots):
+    """64 independent layered 2D shots of uneven size and step count, fp16
+    with the 6-operation compensated update: one batched launch per step
+    (graph-captured runs) against one shot at a time."""
+    import workloads
+    from paper_2310_00236_amd import tuning
+    sizes = workloads.shot_sizes(nshots)
+    shots = [workloads.shot(nx, ny, ns, i) for i, (nx, ny, ns) in enumerate(sizes)]
+    total = sum(s.nx * s.ny * s.nsteps for s in shots)
+
+    def make():
+        plans = []
+        for s in shots:
+            pb = hw.Problem("acoustic2d", s.nx, s.ny, 1, 4, "f16", "twosum",
+                            s.dx, s.dt, 0, 0)
+            p = hw.Plan(pb)
+            p.set_tile(tuning.best_tile("acoustic2d", 4, "f16", "twosum", s.nx, s.ny))
+            p.set_material([s.rho, s.kappa])
+            p.set_fields(s.fields())
+            plans.append(p)
+        return plans
+
+    stream = torch.cuda.current_stream()
+    res = {}
+    for mode in ("batched", "one_shot_at_a_time"):
+        plans = make()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if mode == "batched":
+            hw.batch_advance(plans, [s.nsteps for s in shots])
+        else:
+            for p, s in zip(plans, shots):
+                p.advance(s.nsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[mode] = {"glups": total / (ms * 1e-3) / 1e9, "seconds": ms * 1e-3}
+        for p in plans:
+            p.close()
+        del plans
+        print(f"# batched {mode}: {res[mode]}", file=sys.stderr, flush=True)
+    return {"workload": f"{nshots} layered 2D order-4 shots, sides U{{256..2048}}, "
+                        f"steps U{{500..5000}}, fp16+TwoSum",
+            "cell_steps": total, **res,
+            "speedup": res["batched"]["glups"] / res["one_shot_at_a_time"]["glups"]}
+
+
+def run_serving(hw, torch, nreq, glups2d, glups3d, chunk=200):
+    """Poisson stream of mixed requests (70% 2D order-4 512^2..4096^2, 30% 3D
+    128^3..384^3, 1000..10000 steps, fp32 or fp16+TwoSum), arrival rate set so
+    that the offered work is about 80% of the measured throughput; admission
+    by device footprint; continuous batching in chunks of `chunk` steps."""
+    import workloads
+    from paper_2310_00236_amd import serve
+    probe = workloads.request_stream(nreq, rate=1.0)
+    work = []
+    for r in probe:
+        cells = r.size ** 2 if r.kind == "acoustic2d" else r.size ** 3
+        work.append(cells * r.nsteps / ((glups2d if r.kind == "acoustic2d" else glups3d) * 1e9))
+    rate = 0.8 / (sum(work) / len(work))
+    reqs = workloads.request_stream(nreq, rate=rate)
+    jobs = []
+    t = time.perf_counter()
+    for r in reqs:
+        w = workloads.request_problem(r)
+        storage, comp = ("f32", "none") if r.precision == "f32" else ("f16", "twosum")
+        if r.kind == "acoustic2d":
+            pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, 4, storage, comp, w.dx, w.dt, 0, 0)
+            mat = [w.rho, w.kappa]
+        else:
+            pb = hw.Problem("elastic3d", w.nx, w.ny, w.nz, 2, storage, comp, w.dx, w.dt, 0, 0)
+            mat = [w.rho, w.lam, w.mu]
+        jobs.append(serve.Job(id=r.index, arrival=r.arrival, footprint=hw.footprint(pb),
+                              nsteps=r.nsteps, cells=pb.cells, payload=(pb, mat, w.fields())))
+    gen_s = time.perf_counter() - t
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    summary, done = serve.serve(jobs, budget, chunk_steps=chunk)
+    summary.update({"requests": nreq, "arrival_rate_per_s": rate,
+                    "hbm_budget_bytes": budget, "chunk_steps": chunk,
+                    "input_generation_s": gen_s,
+                    "workload": "Poisson stream, 70% 2D order-4 512^2-4096^2 / 30% 3D "
+                                "128^3-384^3, 1000-10000 steps, fp32 or fp16+TwoSum"})
+    print(f"# serving: {summary}", file=sys.stderr, flush=True)
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -150,6 +292,12 @@ def main():
     ap.add_argument("--variants", default="all",
                     help="comma list of storage+comp, e.g. f16+twosum,f32+none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--elastic-n", type=int, default=512)
+    ap.add_argument("--elastic-steps", type=int, default=2000)
+    ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--only-2d", action="store_true",
+                    help="skip the 3D, batched and serving workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates "
                          "the HBM byte counters against a known size)")
@@ -210,6 +358,13 @@ def main():
         "kernel_ms": head["kernel_ms"],
     }
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    extra = {}
+    if not args.only_2d:
+        extra["elastic3d"] = run_elastic(hw, torch, args.elastic_n, args.elastic_steps,
+                                         20, [("f16", "twosum"), ("f32", "none")])
+        extra["batched"] = run_batched(hw, torch, args.shots)
+        g3 = extra["elastic3d"]["variants"]["f16+twosum"]["glups"]
+        extra["serving"] = run_serving(hw, torch, args.requests, head["glups"], g3)
     f32 = results.get("f32+none")
     out = {
         "metric": METRIC,
@@ -239,7 +394,11 @@ def main():
                      for k, v in results.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        **extra,
     }
+    if "serving" in extra:
+        out["p50_latency_s"] = extra["serving"]["p50_latency_s"]
+        out["p99_latency_s"] = extra["serving"]["p99_latency_s"]
     print(json.dumps(out))
 
 

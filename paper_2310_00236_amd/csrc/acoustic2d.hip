@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void ac2d_step_kernel(const Ac2dBatch a)
             update_store<S, COMP>(v, c, inc);
             vxs[e] = S::load(v);
             if (lx >= 0 && lx < TX && x0 + lx < nx)
-                vx_out[(y0 + ly) * pitch + x0 + lx] = WD::make(v, c);
+                __builtin_nontemporal_store(WD::make(v, c), &vx_out[(y0 + ly) * pitch + x0 + lx]);
         }
     }
 
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void ac2d_step_kernel(const Ac2dBatch a)
             update_store<S, COMP>(v, c, inc);
             vys[e] = S::load(v);
             if (ly >= 0 && ly < TY && y0 + ly < ny)
-                vy_out[(y0 + ly) * pitch + x0 + lx] = WD::make(v, c);
+                __builtin_nontemporal_store(WD::make(v, c), &vy_out[(y0 + ly) * pitch + x0 + lx]);
         }
     }
     __syncthreads();
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kThreads) void ac2d_step_kernel(const Ac2dBatch a)
             const float inc = kr[k] * dv;
             T pv = WD::v(po[k]), c = WD::c(po[k]);
             update_store<S, COMP>(pv, c, inc);
-            p_out[(y0 + ly) * pitch + x0 + lx] = WD::make(pv, c);
+            __builtin_nontemporal_store(WD::make(pv, c), &p_out[(y0 + ly) * pitch + x0 + lx]);
         }
     }
 }

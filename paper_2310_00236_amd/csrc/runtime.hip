@@ -186,7 +186,18 @@ struct hw_plan {
     bool have_material = false, have_fields = false;
     int tile = 0;
     double scale_up = 1.0, scale_down = 1.0;
+    // captured run of kGraphSteps steps starting from field set 0
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_tile = -1;
     KernelKey key() const { return {pb.physics, pb.order, pb.storage, pb.comp}; }
+    ~hw_plan()
+    {
+        if (graph)
+            (void)hipGraphExecDestroy(graph);
+        if (cap_stream)
+            (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace {
@@ -203,9 +214,16 @@ void tile_counts(const hw_plan *p, int tile, int32_t *tx, int32_t *ty, int32_t *
     *total = *tx * *ty * (int32_t)p->pb.nz;
 }
 
-// One time step for a group of plans sharing a kernel, in launches of at
-// most kMaxBatch shots.
-hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s)
+// Steps launched between host interventions are captured into a HIP graph
+// in runs of this many (even, so every shot's field set returns to where the
+// run started).
+constexpr int kGraphSteps = 32;
+
+// Launch one time step for a group of plans sharing a kernel, in launches of
+// at most kMaxBatch shots; parity[i] is plan i's current field set.  Host
+// state is not touched (the same launches can be recorded into a graph).
+hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
+                           const int *parity, hipStream_t s)
 {
     const hw_plan *p0 = plans[0];
     for (int base = 0; base < n; base += kMaxBatch) {
@@ -223,7 +241,7 @@ hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s)
                 a.tile_start[i] = (int32_t)total;
                 a.tiles_x[i] = tx;
                 a.tiles_y[i] = ty;
-                a.parity[i] = p->cur;
+                a.parity[i] = parity[base + i];
                 a.desc[i] = (const Ac2dDesc *)p->d_desc;
                 total += tt;
             }
@@ -256,12 +274,155 @@ hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s)
         if (e != hipSuccess)
             return fail(HW_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
     }
+    return HW_OK;
+}
+
+void advance_state(hw_plan *const *plans, int n, int64_t steps)
+{
     for (int i = 0; i < n; ++i) {
         hw_plan *p = plans[i];
         if (p->pb.physics == HW_ACOUSTIC2D)
-            p->cur ^= 1;
-        p->step += 1;
+            p->cur ^= (int)(steps & 1);
+        p->step += steps;
     }
+}
+
+hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s)
+{
+    std::vector<int> par(n);
+    for (int i = 0; i < n; ++i)
+        par[i] = plans[i]->cur;
+    hw_status st = launch_group_raw(plans, n, tile, par.data(), s);
+    if (st == HW_OK)
+        advance_state(plans, n, 1);
+    return st;
+}
+
+// Record kGraphSteps steps of one group (starting from the plans' current
+// field sets) into an executable graph, via a capture stream.
+hw_status capture_run(hw_plan *const *plans, int n, int tile, hipStream_t cap,
+                      hipGraphExec_t *out)
+{
+    std::vector<int> par(n);
+    for (int i = 0; i < n; ++i)
+        par[i] = plans[i]->cur;
+    HW_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hw_status st = HW_OK;
+    for (int g = 0; g < kGraphSteps && st == HW_OK; ++g) {
+        st = launch_group_raw(plans, n, tile, par.data(), cap);
+        for (int i = 0; i < n; ++i)
+            if (plans[i]->pb.physics == HW_ACOUSTIC2D)
+                par[i] ^= 1;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (st != HW_OK) {
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess)
+        return fail(HW_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return fail(HW_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return HW_OK;
+}
+
+thread_local hipStream_t t_cap_stream = nullptr;
+
+// Batch graphs whose last launch was recorded by an event; destroyed once
+// that event has completed (never while a launch may still be pending).
+struct RetiredGraph {
+    hipGraphExec_t exec;
+    hipEvent_t done;
+};
+thread_local std::vector<RetiredGraph> t_retired;
+
+void reap_graphs(bool wait)
+{
+    for (size_t i = 0; i < t_retired.size();) {
+        RetiredGraph &r = t_retired[i];
+        if (wait)
+            (void)hipEventSynchronize(r.done);
+        if (hipEventQuery(r.done) == hipSuccess) {
+            (void)hipGraphExecDestroy(r.exec);
+            (void)hipEventDestroy(r.done);
+            t_retired[i] = t_retired.back();
+            t_retired.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
+hw_status retire_graph(hipGraphExec_t exec, hipStream_t s)
+{
+    hipEvent_t ev;
+    HW_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HW_HIP(hipEventRecord(ev, s));
+    t_retired.push_back({exec, ev});
+    if (t_retired.size() > 64)
+        reap_graphs(true);
+    return HW_OK;
+}
+
+hw_status capture_stream(hipStream_t *cs)
+{
+    if (!*cs)
+        HW_HIP(hipStreamCreateWithFlags(cs, hipStreamNonBlocking));
+    return HW_OK;
+}
+
+// Advance a group of plans by `steps` steps with no host work in between:
+// whole runs of kGraphSteps replay a captured graph, the rest are launched
+// directly.  A single plan keeps its graph (captured from field set 0).
+hw_status run_steps(hw_plan *const *plans, int n, int tile, int64_t steps,
+                    hipStream_t s)
+{
+    hw_status st;
+    if (steps >= kGraphSteps + 1 && n == 1) {
+        hw_plan *p = plans[0];
+        if (p->cur != 0) {                 // align to the captured field set
+            if ((st = launch_group(plans, 1, tile, s)) != HW_OK)
+                return st;
+            steps -= 1;
+        }
+        if (!p->graph || p->graph_tile != tile) {
+            if (p->graph) {
+                (void)hipGraphExecDestroy(p->graph);
+                p->graph = nullptr;
+            }
+            if ((st = capture_stream(&p->cap_stream)) != HW_OK ||
+                (st = capture_run(plans, 1, tile, p->cap_stream, &p->graph)) != HW_OK)
+                return st;
+            p->graph_tile = tile;
+        }
+        for (; steps >= kGraphSteps; steps -= kGraphSteps) {
+            HW_HIP(hipGraphLaunch(p->graph, s));
+            advance_state(plans, 1, kGraphSteps);
+        }
+    } else if (steps >= 2 * kGraphSteps) {
+        hipGraphExec_t exec = nullptr;
+        reap_graphs(false);
+        if ((st = capture_stream(&t_cap_stream)) != HW_OK ||
+            (st = capture_run(plans, n, tile, t_cap_stream, &exec)) != HW_OK)
+            return st;
+        for (; steps >= kGraphSteps; steps -= kGraphSteps) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) {
+                (void)retire_graph(exec, s);
+                return fail(HW_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+            }
+            advance_state(plans, n, kGraphSteps);
+        }
+        if ((st = retire_graph(exec, s)) != HW_OK)
+            return st;
+    }
+    for (; steps > 0; --steps)
+        if ((st = launch_group(plans, n, tile, s)) != HW_OK)
+            return st;
     return HW_OK;
 }
 
@@ -408,9 +569,13 @@ hw_status advance_one(hw_plan *p, int64_t nsteps, int64_t every, hipStream_t s)
         if ((st = record_energy(p, s)) != HW_OK)
             return st;
     hw_plan *pl[1] = {p};
-    for (int64_t n = 0; n < nsteps; ++n) {
-        if ((st = launch_group(pl, 1, p->tile, s)) != HW_OK)
+    while (nsteps > 0) {
+        int64_t chunk = nsteps;
+        if (every > 0)
+            chunk = std::min(chunk, every - p->step % every);
+        if ((st = run_steps(pl, 1, p->tile, chunk, s)) != HW_OK)
             return st;
+        nsteps -= chunk;
         if (every > 0 && p->step % every == 0)
             if ((st = record_energy(p, s)) != HW_OK)
                 return st;
@@ -798,22 +963,27 @@ hw_status hw_batch_advance(hw_plan *const *plans, int32_t n, const int64_t *nste
                 return st;
     }
     for (;;) {
+        // the active set and every plan's next energy log fix the chunk
         std::map<KernelKey, std::vector<hw_plan *>> groups;
         std::vector<int> active;
+        int64_t chunk = INT64_MAX;
         for (int i = 0; i < n; ++i)
             if (left[i] > 0) {
                 groups[plans[i]->key()].push_back(plans[i]);
                 active.push_back(i);
+                chunk = std::min(chunk, left[i]);
+                if (energy_every > 0)
+                    chunk = std::min(chunk, energy_every - plans[i]->step % energy_every);
             }
         if (active.empty())
             break;
         for (auto &g : groups) {
             const int t = tile >= 0 ? tile : g.second[0]->tile;
-            if ((st = launch_group(g.second.data(), (int)g.second.size(), t, s)) != HW_OK)
+            if ((st = run_steps(g.second.data(), (int)g.second.size(), t, chunk, s)) != HW_OK)
                 return st;
         }
         for (int i : active) {
-            left[i] -= 1;
+            left[i] -= chunk;
             hw_plan *p = plans[i];
             if (energy_every > 0 && p->step % energy_every == 0)
                 if ((st = record_energy(p, s)) != HW_OK)
