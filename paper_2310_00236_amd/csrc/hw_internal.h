@@ -51,19 +51,31 @@ struct BatchArgs {
 };
 
 using Ac2dBatch = BatchArgs<Ac2dDesc>;
+
+// Arguments of a launch for one plan: the descriptor travels by value.
+struct Ac2dOne {
+    Ac2dDesc d;
+    int32_t parity, tiles_x, total_tiles;
+};
 using El3dBatch = BatchArgs<El3dDesc>;
 
-struct TileShape { int tx, ty; };
+// kind 0: a workgroup owns a tx by ty tile; kind 1: a workgroup marches
+// down a strip tx wide and ty rows tall.
+struct TileShape { int tx, ty, kind; };
 
 // Tile shapes compiled into the library (x by y cells per workgroup).
-constexpr TileShape kTiles2D[] = {{64, 16}, {128, 8}, {256, 4}, {64, 8}, {128, 16}};
-constexpr TileShape kTiles3D[] = {{64, 4}, {128, 2}, {256, 1}, {32, 8}};
+// 2D: the width is 64 lanes times 1, 2 or 4 cells per lane
+constexpr TileShape kTiles2D[] = {{64, 16, 0}, {64, 32, 0}, {128, 16, 0},
+                                  {64, 64, 1}, {64, 128, 1}, {128, 64, 1}, {128, 128, 1}};
+constexpr TileShape kTiles3D[] = {{64, 4, 0}, {128, 2, 0}, {256, 1, 0}, {32, 8, 0}};
 constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
 constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
 
 // Launchers (one translation unit per physics).
-hipError_t launch_ac2d_step(const Ac2dBatch &a, int storage, int comp,
-                            int order, int tile, hipStream_t s);
+// one: the host copy of the descriptor when the launch covers a single plan
+// (it is then passed by value), else nullptr
+hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
+                            int comp, int order, int tile, hipStream_t s);
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
                               int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);

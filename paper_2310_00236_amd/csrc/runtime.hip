@@ -249,7 +249,8 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
                 return fail(HW_E_INVAL, "batch has too many tiles for one launch");
             a.tile_start[m] = (int32_t)total;
             a.total_tiles = (int32_t)total;
-            e = launch_ac2d_step(a, p0->pb.storage, p0->pb.comp, p0->pb.order, tile, s);
+            e = launch_ac2d_step(a, m == 1 ? &plans[base]->h2 : nullptr,
+                                 p0->pb.storage, p0->pb.comp, p0->pb.order, tile, s);
         } else {
             El3dBatch a;
             std::memset(&a, 0, sizeof(a));
