@@ -124,13 +124,18 @@ def cpu_baseline(w, target_s=15.0):
     f, c, _ = oracle.acoustic2d(*args, f, storage="f16", stencil="f32",
                                 comp="twosum", nsteps=1)
     t1 = time.perf_counter() - t
-    more = max(0, int(target_s / t1) - 1)
+    t = time.perf_counter()
+    f, c, _ = oracle.acoustic2d(*args, f, storage="f16", stencil="f32",
+                                comp="twosum", comps=c, nsteps=1)
+    t2 = time.perf_counter() - t
+    t1 += t2
+    more = max(0, int((target_s - t1) / t2))
     t = time.perf_counter()
     if more:
         oracle.acoustic2d(*args, f, storage="f16", stencil="f32", comp="twosum",
                           comps=c, nsteps=more)
     tm = time.perf_counter() - t
-    steps = 1 + more
+    steps = 2 + more
     secs = t1 + tm
     return {"value": w.nx * w.ny * steps / secs / 1e9, "unit": "GLUPS",
             "cores": oracle.max_threads(), "kind": "oracle",
@@ -296,8 +301,9 @@ def main():
     ap.add_argument("--elastic-steps", type=int, default=2000)
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--only-2d", action="store_true",
-                    help="skip the 3D, batched and serving workloads")
+    ap.add_argument("--sections", default="2d,3d,batched,serving",
+                    help="comma list of workloads to run: 2d (always reported), "
+                         "3d, batched, serving")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates "
                          "the HBM byte counters against a known size)")
@@ -359,10 +365,13 @@ def main():
     }
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     extra = {}
-    if not args.only_2d:
+    sections = set(args.sections.split(","))
+    if "3d" in sections or "serving" in sections:
         extra["elastic3d"] = run_elastic(hw, torch, args.elastic_n, args.elastic_steps,
                                          20, [("f16", "twosum"), ("f32", "none")])
+    if "batched" in sections:
         extra["batched"] = run_batched(hw, torch, args.shots)
+    if "serving" in sections:
         g3 = extra["elastic3d"]["variants"]["f16+twosum"]["glups"]
         extra["serving"] = run_serving(hw, torch, args.requests, head["glups"], g3)
     f32 = results.get("f32+none")
