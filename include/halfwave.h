@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define HW_ABI_VERSION 1u
+#define HW_ABI_VERSION 2u
 
 typedef enum hw_status {
     HW_OK = 0,
@@ -181,12 +181,18 @@ hw_status hw_state_export(hw_plan *plan, void *blob, size_t bytes,
 hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
                           void *stream);
 
-/* Kernel tile shapes (x by y cells per workgroup) the library was built
- * with.  hw_plan_set_tile picks one for a plan; every tile shape gives
- * bit-identical results. */
+/* Kernel shapes the library was built with, by index.  tx by ty cells of
+ * a plane per workgroup; tz planes per workgroup; kind:
+ *   acoustic2d  0 = one tile per workgroup, 1 = a workgroup marches down a
+ *               strip ty rows tall;
+ *   elastic3d   0 = two passes per step (velocities, then stresses), one
+ *               plane per workgroup; 2 = one fused pass per step, a
+ *               workgroup walks a tx by ty column through tz planes.
+ * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
+ * results.  Any of the output pointers may be NULL. */
 int32_t hw_tile_count(int32_t physics);
 hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx,
-                       int32_t *ty);
+                       int32_t *ty, int32_t *tz, int32_t *kind);
 hw_status hw_plan_set_tile(hw_plan *plan, int32_t tile);
 
 /* Advance n plans (0 < n) by nsteps[i] steps each, batching all plans with

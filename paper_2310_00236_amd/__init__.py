@@ -29,7 +29,7 @@ ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
 STATUS = {0: "HW_OK", 1: "HW_E_INVAL", 2: "HW_E_UNSTABLE", 3: "HW_E_RANGE",
           4: "HW_E_NOMEM", 5: "HW_E_DEVICE", 6: "HW_E_NONFINITE",
           7: "HW_E_STATE"}
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 
 class HalfwaveError(RuntimeError):
@@ -93,7 +93,8 @@ def lib():
         "hw_state_export": (I32, [PPlan, P, ctypes.c_size_t, P]),
         "hw_state_import": (I32, [PPlan, P, ctypes.c_size_t, P]),
         "hw_tile_count": (I32, [I32]),
-        "hw_tile_info": (I32, [I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32)]),
+        "hw_tile_info": (I32, [I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
+                               ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "hw_plan_set_tile": (I32, [PPlan, I32]),
         "hw_batch_advance": (I32, [ctypes.POINTER(P), I32, PI64, I64, I32, P]),
         "hw_simulate": (I32, [PProb, PPD, PPD, I64, I64, PD, I64, PI64, P,
@@ -186,13 +187,19 @@ def cfl_bound(physics: str, order: int) -> float:
 
 
 def tiles(physics: str):
+    """Kernel shapes by index: (tx, ty, tz, kind) as hw_tile_info."""
     ph = {"acoustic2d": 0, "elastic3d": 1}[physics]
     out = []
     for t in range(lib().hw_tile_count(ph)):
-        tx, ty = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().hw_tile_info(ph, t, ctypes.byref(tx), ctypes.byref(ty)))
-        out.append((tx.value, ty.value))
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().hw_tile_info(ph, t, *[ctypes.byref(x) for x in v]))
+        out.append(tuple(x.value for x in v))
     return out
+
+
+def tile_label(shape) -> str:
+    tx, ty, tz, kind = shape
+    return f"{tx}x{ty}" + (f"x{tz}" if tz > 1 else "") + f"/k{kind}"
 
 
 class Plan:

@@ -26,13 +26,14 @@ struct Ac2dDesc {
     void *vx[2], *vy[2], *p[2];   // field sets (storage words)
 };
 
-// Device-resident description of one 3D elastic plan (updated in place by
-// a velocity pass followed by a stress pass); same word layout.
+// Device-resident description of one 3D elastic plan; same word layout.
+// The nine fields ping-pong between two sets like the 2D fields: a step
+// reads set n and writes set n+1.
 struct El3dDesc {
     int64_t nx, ny, nz, pitch, slab;
     float w;                      // dt/dx (fp32)
     const float *b, *lam, *mu;    // at cell centres
-    void *f[9];                   // vx vy vz sxx syy szz sxy sxz syz
+    void *f[2][9];                // vx vy vz sxx syy szz sxy sxz syz
 };
 
 // Arguments of one batched launch: the shots it covers, the parity (which
@@ -58,16 +59,28 @@ struct Ac2dOne {
     int32_t parity, tiles_x, total_tiles;
 };
 using El3dBatch = BatchArgs<El3dDesc>;
+struct El3dOne {
+    El3dDesc d;
+    int32_t parity, tiles_x, tiles_y, total_tiles;
+};
 
-// kind 0: a workgroup owns a tx by ty tile; kind 1: a workgroup marches
-// down a strip tx wide and ty rows tall.
-struct TileShape { int tx, ty, kind; };
+// Tile shapes compiled into the library (x by y cells per workgroup, and
+// the z planes one workgroup walks through for the marching 3D kernel).
+//   2D kind 0: a workgroup owns a tx by ty tile;
+//   2D kind 1: a workgroup marches down a strip tx wide and ty rows tall;
+//   3D kind 0: two passes (velocities, then stresses), one tx by ty tile of
+//              one z plane per workgroup;
+//   3D kind 2: one fused pass, a workgroup walks a tx by ty column through
+//              tz planes.
+struct TileShape { int tx, ty, kind, tz; };
 
-// Tile shapes compiled into the library (x by y cells per workgroup).
 // 2D: the width is 64 lanes times 1, 2 or 4 cells per lane
-constexpr TileShape kTiles2D[] = {{64, 16, 0}, {64, 32, 0}, {128, 16, 0},
-                                  {64, 64, 1}, {64, 128, 1}, {128, 64, 1}, {128, 128, 1}};
-constexpr TileShape kTiles3D[] = {{64, 4, 0}, {128, 2, 0}, {256, 1, 0}, {32, 8, 0}};
+constexpr TileShape kTiles2D[] = {{64, 16, 0, 1}, {64, 32, 0, 1}, {128, 16, 0, 1},
+                                  {64, 64, 1, 1}, {64, 128, 1, 1}, {128, 64, 1, 1},
+                                  {128, 128, 1, 1}};
+constexpr TileShape kTiles3D[] = {{64, 4, 0, 1},    {256, 1, 0, 1},   {64, 6, 2, 128},
+                                  {64, 6, 2, 64},   {64, 6, 2, 512},  {64, 10, 2, 128},
+                                  {64, 14, 2, 128}};
 constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
 constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
 
@@ -79,9 +92,9 @@ hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
                               int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);
-hipError_t launch_el3d_step(const El3dBatch &a, int storage, int comp,
-                            int tile, hipStream_t s);
-hipError_t launch_el3d_energy(const El3dDesc *d_desc, int64_t rows,
+hipError_t launch_el3d_step(const El3dBatch &a, const El3dDesc *one, int storage,
+                            int comp, int tile, hipStream_t s);
+hipError_t launch_el3d_energy(const El3dDesc *d_desc, int parity, int64_t rows,
                               int storage, int stride, double *partial,
                               hipStream_t s);
 hipError_t launch_energy_finish(const double *partial, int64_t n,

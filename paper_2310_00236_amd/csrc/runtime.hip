@@ -122,7 +122,7 @@ Layout make_layout(const hw_problem *pb)
     const bool ac = pb->physics == HW_ACOUSTIC2D;
     L.nf = ac ? 3 : 9;
     L.nm = ac ? 2 : 3;
-    L.sets = ac ? 2 : 1;
+    L.sets = 2;
     L.pitch = (pb->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
     L.slab = L.pitch * pb->ny;
     L.rows = pb->ny * pb->nz;
@@ -211,7 +211,7 @@ void tile_counts(const hw_plan *p, int tile, int32_t *tx, int32_t *ty, int32_t *
     const TileShape t = p->pb.physics == HW_ACOUSTIC2D ? kTiles2D[tile] : kTiles3D[tile];
     *tx = (int32_t)((p->pb.nx + t.tx - 1) / t.tx);
     *ty = (int32_t)((p->pb.ny + t.ty - 1) / t.ty);
-    *total = *tx * *ty * (int32_t)p->pb.nz;
+    *total = *tx * *ty * (int32_t)((p->pb.nz + t.tz - 1) / t.tz);
 }
 
 // Steps launched between host interventions are captured into a HIP graph
@@ -263,6 +263,7 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
                 a.tile_start[i] = (int32_t)total;
                 a.tiles_x[i] = tx;
                 a.tiles_y[i] = ty;
+                a.parity[i] = parity[base + i];
                 a.desc[i] = (const El3dDesc *)p->d_desc;
                 total += tt;
             }
@@ -270,7 +271,8 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
                 return fail(HW_E_INVAL, "batch has too many tiles for one launch");
             a.tile_start[m] = (int32_t)total;
             a.total_tiles = (int32_t)total;
-            e = launch_el3d_step(a, p0->pb.storage, p0->pb.comp, tile, s);
+            e = launch_el3d_step(a, m == 1 ? &plans[base]->h3 : nullptr,
+                                 p0->pb.storage, p0->pb.comp, tile, s);
         }
         if (e != hipSuccess)
             return fail(HW_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
@@ -282,8 +284,7 @@ void advance_state(hw_plan *const *plans, int n, int64_t steps)
 {
     for (int i = 0; i < n; ++i) {
         hw_plan *p = plans[i];
-        if (p->pb.physics == HW_ACOUSTIC2D)
-            p->cur ^= (int)(steps & 1);
+        p->cur ^= (int)(steps & 1);
         p->step += steps;
     }
 }
@@ -312,8 +313,7 @@ hw_status capture_run(hw_plan *const *plans, int n, int tile, hipStream_t cap,
     for (int g = 0; g < kGraphSteps && st == HW_OK; ++g) {
         st = launch_group_raw(plans, n, tile, par.data(), cap);
         for (int i = 0; i < n; ++i)
-            if (plans[i]->pb.physics == HW_ACOUSTIC2D)
-                par[i] ^= 1;
+            par[i] ^= 1;
     }
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cap, &graph);
@@ -439,7 +439,7 @@ hw_status record_energy(hw_plan *p, hipStream_t s)
                                p->partial, s);
     } else {
         factor *= p->pb.dx;
-        e = launch_el3d_energy((const El3dDesc *)p->d_desc, p->L.rows,
+        e = launch_el3d_energy((const El3dDesc *)p->d_desc, p->cur, p->L.rows,
                                p->pb.storage, p->L.words, p->partial, s);
     }
     if (e == hipSuccess)
@@ -687,8 +687,9 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
         d.b = p->mat[0];
         d.lam = p->mat[1];
         d.mu = p->mat[2];
-        for (int f = 0; f < 9; ++f)
-            d.f[f] = p->fld[0][f];
+        for (int s = 0; s < 2; ++s)
+            for (int f = 0; f < 9; ++f)
+                d.f[s][f] = p->fld[s][f];
     }
     *out = p;
     return HW_OK;
@@ -911,7 +912,8 @@ int32_t hw_tile_count(int32_t physics)
     return physics == HW_ACOUSTIC2D ? kNumTiles2D : physics == HW_ELASTIC3D ? kNumTiles3D : 0;
 }
 
-hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx, int32_t *ty)
+hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx, int32_t *ty,
+                       int32_t *tz, int32_t *kind)
 {
     if (tile < 0 || tile >= hw_tile_count(physics))
         return fail(HW_E_INVAL, "tile index out of range");
@@ -920,6 +922,10 @@ hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx, int32_t *ty)
         *tx = t.tx;
     if (ty)
         *ty = t.ty;
+    if (tz)
+        *tz = t.tz;
+    if (kind)
+        *kind = t.kind;
     return HW_OK;
 }
 

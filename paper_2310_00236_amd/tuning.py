@@ -97,7 +97,7 @@ def tune(problem, material, fields, steps=50, reps=3, device="cuda:0",
         k = key(problem.physics, problem.order, problem.storage, problem.comp,
                 problem.nx, problem.ny, problem.nz)
         tab[k] = {"tile": best_t, "shape": list(tiles[best_t]),
-                  "ms_per_step": {f"{tiles[t][0]}x{tiles[t][1]}": v
+                  "ms_per_step": {hw.tile_label(tiles[t]): v
                                   for t, v in times.items()}}
         with open(TABLE, "w") as f:
             json.dump(tab, f, indent=1, sort_keys=True)

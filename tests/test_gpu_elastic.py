@@ -10,15 +10,16 @@ from helpers import (ST, assert_bitexact, elastic_fields, gpu_elastic,
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.parametrize("tile", [0, 2])
 @pytest.mark.parametrize("storage", ST)
 @pytest.mark.parametrize("comp", ["none", "fast2sum", "twosum"])
-def test_bitexact_vs_emulation(storage, comp):
+def test_bitexact_vs_emulation(storage, comp, tile):
     nx, ny, nz = 70, 11, 7        # ragged in x and y for every tile shape
     rho, lam, mu, cp = smooth_medium3d(nx, ny, nz, 201)
     dt = 0.4 * hw.cfl_bound("elastic3d", 2) / cp
     f = elastic_fields(nx, ny, nz, 202)
     g, gc, ge = gpu_elastic(nx, ny, nz, storage, comp, dt, rho, lam, mu, f, 12,
-                            energy_every=4)
+                            energy_every=4, tile=tile)
     w, wc, we = oracle_elastic(nx, ny, nz, storage, comp, dt, rho, lam, mu, f,
                                12, energy_every=4)
     assert_bitexact(g, w, "fields")
@@ -27,8 +28,9 @@ def test_bitexact_vs_emulation(storage, comp):
     np.testing.assert_allclose(ge, we, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 1), (5, 4, 3), (33, 9, 2)])
-@pytest.mark.parametrize("tile", range(4))
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 1), (5, 4, 3), (33, 9, 2),
+                                   (130, 13, 9), (9, 7, 130)])
+@pytest.mark.parametrize("tile", range(len(hw.tiles("elastic3d"))))
 def test_bitexact_sizes_and_tiles(shape, tile):
     nx, ny, nz = shape
     rho, lam, mu, cp = smooth_medium3d(nx, ny, nz, 203)

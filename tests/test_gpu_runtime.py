@@ -34,10 +34,12 @@ def _elastic_plan(n, storage, comp, seed, trace_cap=64):
     return plan
 
 
-def test_batch_bit_identical_to_single_runs():
+@pytest.mark.parametrize("tile", [1, 2])
+def test_batch_bit_identical_to_single_runs(tile):
     """Mixed batch: uneven 2D shots of two precisions, 3D shots, uneven step
     counts; every plan ends bit-identical to running it alone, energy traces
-    included."""
+    included.  Tile 1 runs the 3D shots through the two-pass kernels, tile 2
+    through the fused marching kernel."""
     specs = [("a", 300, 170, "f16", "twosum", 37), ("a", 129, 400, "f16", "twosum", 20),
              ("a", 64, 64, "f32", "none", 45), ("a", 250, 33, "f16", "twosum", 0),
              ("e", 20, "f16", "twosum", 15), ("e", 12, "f32", "none", 9)]
@@ -49,7 +51,7 @@ def test_batch_bit_identical_to_single_runs():
 
     steps = [s[-1] for s in specs]
     batch = [make(s, 300 + 10 * i) for i, s in enumerate(specs)]
-    hw.batch_advance(batch, steps, energy_every=5, tile=1)
+    hw.batch_advance(batch, steps, energy_every=5, tile=tile)
     alone = [make(s, 300 + 10 * i) for i, s in enumerate(specs)]
     for p, n in zip(alone, steps):
         p.advance(n, energy_every=5)
