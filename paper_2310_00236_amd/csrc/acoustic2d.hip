@@ -86,6 +86,23 @@ __device__ __forceinline__ Cells<W, V> load_cells(const W HW_GLOBAL *p)
     return c;
 }
 
+// The same with non-temporal loads, for words that only one workgroup reads
+// (they need not stay in L2 for a neighbouring tile's halo).
+template <class W, int V>
+__device__ __forceinline__ Cells<W, V> load_cells_nt(const W HW_GLOBAL *p)
+{
+    constexpr int BYTES = V * (int)sizeof(W);
+    constexpr int PIECE = BYTES < 16 ? BYTES : 16;
+    using R = typename RawOf<PIECE>::type;
+    R r[BYTES / PIECE];
+#pragma unroll
+    for (int i = 0; i < BYTES / PIECE; ++i)
+        r[i] = __builtin_nontemporal_load(((const R HW_GLOBAL *)p) + i);
+    Cells<W, V> c;
+    __builtin_memcpy(&c, r, BYTES);
+    return c;
+}
+
 template <class W, int V>
 __device__ __forceinline__ void store_cells_nt(W HW_GLOBAL *p, const Cells<W, V> &c)
 {
@@ -211,6 +228,14 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
             return c;
         }
     };
+    // words only this workgroup reads: non-temporal loads
+    auto ldw_nt = [&](const W HW_GLOBAL *base, int row) {
+        if constexpr (!WX) {
+            return load_cells_nt<W, V>(base + row + x0 + xl);
+        } else {
+            return ldw(base, row);
+        }
+    };
     // Halo columns: the cells of a region left and right of the tile, all
     // rows together, enumerated e = 0 .. NH-1 and handled one per thread,
     // so a whole region's halo costs one instruction per wavefront.  Element
@@ -276,12 +301,12 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
         const int ly = wv + 4 * k;
         if (y0 + ly < ny) {
             const int row = (y0 + ly) * pitch;
-            vxw[k] = ldw(vx_in, row);
+            vxw[k] = ldw_nt(vx_in, row);
             if constexpr (!WX) {
                 const float HW_GLOBAL *q = kap + row + x0 + xl;
 #pragma unroll
                 for (int i = 0; i < V; ++i)
-                    km[k][i] = q[i];
+                    km[k][i] = __builtin_nontemporal_load(q + i);
             } else {
 #pragma unroll
                 for (int i = 0; i < V; ++i)
