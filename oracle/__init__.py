@@ -72,8 +72,10 @@ def lib():
         L.orc_max_threads.restype = I
         L.orc_max_threads.argtypes = []
         L.orc_acoustic2d.restype = I
+        PL = ctypes.POINTER(ctypes.c_long)
         L.orc_acoustic2d.argtypes = [Lg, Lg, I, D, D, P, P, P, P, P, P, P, P,
-                                     I, I, I, Lg, Lg, P, I]
+                                     I, I, I, Lg, Lg, P, I,
+                                     Lg, Lg, P, Lg, Lg, PL, PL, P]
         L.orc_acoustic2d_energy.restype = D
         L.orc_acoustic2d_energy.argtypes = [Lg, Lg, I, D, D, P, P, P, P, P]
         L.orc_elastic3d.restype = I
@@ -136,13 +138,21 @@ def eft_check(fmt: str, which: int, a, b, require_order: bool) -> int:
 
 def acoustic2d(nx, ny, order, dx, dt, rho, kappa, fields, *, storage="f64",
                stencil="f64", comp="none", comps=None, nsteps=0,
-               energy_every=0, nthreads=0):
+               energy_every=0, nthreads=0, source=None, receivers=None):
     """Advance the 2D acoustic system (Eq. 1) by nsteps leapfrog steps.
 
     fields: dict with 'vx', 'vy', 'p' ([ny, nx] arrays holding values of the
     storage format, state (v^{n-1/2}, p^n)); comps: same keys for the
     compensation terms (zeros if None).  rho, kappa at p points.
-    Returns (fields, comps, energy) with energy[m] = E at step m*energy_every.
+    source: (ix, iy, samples) -- a point source on the pressure (the s_p
+    term of Eq. 1): step n of this call adds samples[n] (rounded to the
+    stencil format) to the pressure right-hand side at cell (ix, iy) before
+    the division by beta, for n < len(samples).
+    receivers: list of (ix, iy) cells; after step n, trace[n, r] holds
+    (p^{n+1}, vx^{n+1/2}, vy^{n+1/2}) at cell r.
+    Returns (fields, comps, energy) with energy[m] = E at step
+    m*energy_every, plus the receiver trace [nsteps, nrec, 3] when receivers
+    are given.
     """
     shape = (ny, nx)
     rho = _f64(rho, shape)
@@ -155,13 +165,26 @@ def acoustic2d(nx, ny, order, dx, dt, rho, kappa, fields, *, storage="f64",
         c = {k: None for k in ACOUSTIC_FIELDS}
     ne = nsteps // energy_every + 1 if energy_every > 0 else 0
     energy = np.zeros(max(ne, 1))
+    sx, sy, samples = (0, 0, np.zeros(1)) if source is None else source
+    samples = np.ascontiguousarray(samples, dtype=np.float64)
+    nsrc = 0 if source is None else len(samples)
+    rec = [] if receivers is None else list(receivers)
+    PL = ctypes.POINTER(ctypes.c_long)
+    rx = np.ascontiguousarray([r[0] for r in rec] or [0], dtype=np.int64)
+    ry = np.ascontiguousarray([r[1] for r in rec] or [0], dtype=np.int64)
+    trace = np.zeros((max(nsteps, 1), max(len(rec), 1), 3))
     rc = lib().orc_acoustic2d(nx, ny, order, dx, dt, _ptr(rho), _ptr(kappa),
                               _ptr(f["vx"]), _ptr(f["vy"]), _ptr(f["p"]),
                               _ptr(c["vx"]), _ptr(c["vy"]), _ptr(c["p"]),
                               FORMATS[storage], FORMATS[stencil], COMPS[comp],
-                              nsteps, energy_every, _ptr(energy), nthreads)
+                              nsteps, energy_every, _ptr(energy), nthreads,
+                              int(sx), int(sy), _ptr(samples), nsrc, len(rec),
+                              rx.ctypes.data_as(PL), ry.ctypes.data_as(PL),
+                              _ptr(trace))
     if rc != 0:
         raise ValueError("oracle rejected the acoustic2d arguments")
+    if receivers is not None:
+        return f, c, energy[:ne], trace[:nsteps, :len(rec)]
     return f, c, energy[:ne]
 
 

@@ -82,12 +82,21 @@ def acoustic2d_operators(nx, ny, order, dx, dt, rho, kappa):
     return Gx, Gy, Dx, Dy, bx, by, kap
 
 
-def acoustic2d_step(ops, vx, vy, p):
-    """One fp64 leapfrog step with the dense operators (flattened fields)."""
+def acoustic2d_step(ops, vx, vy, p, source=None):
+    """One fp64 leapfrog step with the dense operators (flattened fields).
+
+    source: optional (flat index of a p point, value) -- a point source on
+    the pressure equation (the s_p of Eq. 1), a unit vector at that point
+    times the value, added to the divergence before the scaling by kappa."""
     Gx, Gy, Dx, Dy, bx, by, kap = ops
     vx = vx + bx * (Gx @ p)
     vy = vy + by * (Gy @ p)
-    p = p + kap * (Dx @ vx + Dy @ vy)
+    rhs = Dx @ vx + Dy @ vy
+    if source is not None:
+        e = np.zeros_like(rhs)
+        e[source[0]] = 1.0
+        rhs = rhs + source[1] * e
+    p = p + kap * rhs
     return vx, vy, p
 
 

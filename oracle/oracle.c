@@ -265,7 +265,8 @@ static void ac2d_free(ac2d *G)
  * from v^{n+1/2}.  In place, as in Alg. 1/2: the velocity loops read only
  * p, and the pressure loop reads only the new velocities and p itself. */
 static void ac2d_step(const ac2d *G, const arith *A, double *vx, double *vy,
-                      double *p, double *cvx, double *cvy, double *cp)
+                      double *p, double *cvx, double *cvy, double *cp,
+                      long src_q, double src_val)
 {
     const int sf = A->sf;
     const long nx = G->nx, ny = G->ny;
@@ -326,6 +327,11 @@ static void ac2d_step(const ac2d *G, const arith *A, double *vx, double *vy,
             }
             double d = S(gx + gy);
             long q = j * nx + i;
+            /* point source (Eq. 1, s_p): the sample joins the right-hand
+             * side before the division by beta, as in the source line of
+             * Alg. 1/2; it is held in the stencil format */
+            if (q == src_q)
+                d = S(d + S(src_val));
             double inc = S(G->k[q] * d);
             update(A, &p[q], cp ? &cp[q] : NULL, inc);
         }
@@ -397,18 +403,33 @@ int orc_max_threads(void)
  * Fields vx, vy, p (and the compensation arrays, which may be NULL when
  * comp == COMP_NONE) hold values of the storage format on entry.  If
  * energy_every > 0, energy[m] receives E at step m*energy_every for
- * m = 0 .. nsteps/energy_every.  Returns 0, or -1 on bad arguments. */
+ * m = 0 .. nsteps/energy_every.
+ * Point source: if nsrc > 0, step n (n = 0 .. nsteps-1, counted from this
+ * call) adds src[n] (for n < nsrc) to the pressure right-hand side at cell
+ * (src_x, src_y).  Receivers: if nrec > 0, after step n the values p^{n+1},
+ * vx^{n+1/2}, vy^{n+1/2} at cell (rec_x[r], rec_y[r]) are written to
+ * rec_out[(n*nrec + r)*3 + 0, 1, 2].  Returns 0, or -1 on bad arguments. */
 int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
                    const double *rho, const double *kappa, double *vx,
                    double *vy, double *p, double *cvx, double *cvy,
                    double *cp, int storage, int stencil, int comp,
                    long nsteps, long energy_every, double *energy,
-                   int nthreads)
+                   int nthreads, long src_x, long src_y, const double *src,
+                   long nsrc, long nrec, const long *rec_x,
+                   const long *rec_y, double *rec_out)
 {
     if (nx < 1 || ny < 1 || (order != 2 && order != 4) || nsteps < 0)
         return -1;
     if (comp != COMP_NONE && (!cvx || !cvy || !cp))
         return -1;
+    if (nsrc > 0 && (!src || src_x < 0 || src_x >= nx || src_y < 0 ||
+                     src_y >= ny))
+        return -1;
+    if (nrec > 0 && (!rec_x || !rec_y || !rec_out))
+        return -1;
+    for (long r = 0; r < nrec; ++r)
+        if (rec_x[r] < 0 || rec_x[r] >= nx || rec_y[r] < 0 || rec_y[r] >= ny)
+            return -1;
     set_threads(nthreads);
     ac2d G;
     ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa);
@@ -417,7 +438,16 @@ int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
     if (energy_every > 0)
         energy[m++] = ac2d_energy(&G, dx, vx, vy, p);
     for (long n = 1; n <= nsteps; ++n) {
-        ac2d_step(&G, &A, vx, vy, p, cvx, cvy, cp);
+        const long src_q = n - 1 < nsrc ? src_y * nx + src_x : -1;
+        ac2d_step(&G, &A, vx, vy, p, cvx, cvy, cp, src_q,
+                  src_q >= 0 ? src[n - 1] : 0.0);
+        for (long r = 0; r < nrec; ++r) {
+            const long q = rec_y[r] * nx + rec_x[r];
+            double *o = rec_out + ((n - 1) * nrec + r) * 3;
+            o[0] = p[q];
+            o[1] = vx[q];
+            o[2] = vy[q];
+        }
         if (energy_every > 0 && n % energy_every == 0)
             energy[m++] = ac2d_energy(&G, dx, vx, vy, p);
     }

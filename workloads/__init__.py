@@ -24,6 +24,11 @@ smooth random medium below stands in for it):
   shots     64 independent layered 2D shots, sides U{256..2048}, step counts
             U{500..5000}.
   requests  Poisson stream of mixed 2D layered / 3D smooth requests.
+  paper2d   the acoustic experiment of Sec. 3: homogeneous rho = c = 1,
+            600 x 600 cells of 1/125 m (ppw = 10; 1800 x 1800 of 1/375 m for
+            ppw = 30), dt = 1e-4 s, 60000 steps, order 4, at rest; a point
+            source on the pressure with a 5 Hz Ricker wavelet at one third
+            of the domain in both directions, a receiver at two thirds.
 """
 from __future__ import annotations
 
@@ -126,6 +131,9 @@ class Acoustic2D:
     nsteps: int = 0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # point source on the pressure: (ix, iy, per-step samples), see paper2d
+    source: tuple | None = None
+    receivers: list | None = None      # [(ix, iy), ...]
 
     @property
     def cells(self) -> int:
@@ -170,6 +178,44 @@ def small2d(n=128, nsteps=1000, order=2, cfl=0.5, sigma=8.0) -> Acoustic2D:
     return Acoustic2D(n, n, order, 1.0, dt, ones, ones.copy(),
                       gaussian2d(n, n, n // 2, n // 2, sigma), nsteps=nsteps,
                       name=f"acoustic2d-o{order}-{n}x{n}-homogeneous")
+
+
+def ricker(t, f0):
+    """Ricker wavelet of peak frequency f0 at times t (seconds, centred on
+    the peak): (1 - 2a) exp(-a) with a = (pi f0 t)^2."""
+    a = (math.pi * f0 * np.asarray(t, dtype=np.float64)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def paper2d(ppw=10, nsteps=60000, order=4, f0=5.0, delay=None,
+            amplitude=1.0) -> Acoustic2D:
+    """The acoustic setup of Sec. 3 (homogeneous, at rest, Ricker point
+    source on the pressure, one receiver).
+
+    The grid has 600 * ppw / 10 cells per side with dx = (1/125) * 10 / ppw
+    (the baseline's 12.5 Hz maximal frequency at ppw points per wavelength
+    of c = 1 m/s) and dt = 1e-4 s.  Per-step source samples: the scheme's
+    right-hand sides already carry dt (the stencil weights are c_k dt/dx)
+    and a point source spreads over one cell of area dx*dx, so step n adds
+    amplitude * dt / dx^2 * ricker(t_{n+1/2} - delay) with t_{n+1/2} =
+    (n + 1/2) dt, the time at which the pressure update is centred.  The
+    wavelet is delayed by 1.2 / f0 so that it starts at rest (|r| < 2e-5 at
+    t = 0)."""
+    n = 600 * ppw // 10
+    dx = (1.0 / 125.0) * 10.0 / ppw
+    dt = 1e-4
+    delay = 1.2 / f0 if delay is None else delay
+    t = (np.arange(nsteps) + 0.5) * dt - delay
+    samples = amplitude * dt / (dx * dx) * ricker(t, f0)
+    # the wavelet is negligible after delay + 1.2/f0: keep only that part
+    keep = int(np.ceil((delay + 1.2 / f0) / dt)) + 1
+    samples = samples[:min(keep, nsteps)]
+    ones = np.ones((n, n))
+    return Acoustic2D(n, n, order, dx, dt, ones, ones.copy(), np.zeros((n, n)),
+                      nsteps=nsteps, name=f"acoustic2d-o{order}-{n}x{n}-ricker-ppw{ppw}",
+                      meta={"ppw": ppw, "f0": f0, "delay": delay},
+                      source=(n // 3, n // 3, samples),
+                      receivers=[(2 * n // 3, 2 * n // 3)])
 
 
 def layered2d(nx=4096, ny=None, nsteps=10000, order=4, cfl=0.4, nlayers=4,
