@@ -245,6 +245,106 @@ def run_batched(hw, torch, nshots):
             "speedup": res["batched"]["glups"] / res["one_shot_at_a_time"]["glups"]}
 
 
+PAPER_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
+                            "golden", "paper2d_ppw10_fp64.csv")
+PAPER_VARIANTS = [("f32", "none"), ("f16", "none"), ("f16", "fast2sum"),
+                  ("f16", "twosum"), ("bf16", "none"), ("bf16", "twosum")]
+
+
+def read_paper_golden(path=PAPER_GOLDEN):
+    """The FP64 oracle's receiver trace (every 50th step) and energy (every
+    500th) of the Sec. 3 experiment, or None if it has not been generated."""
+    if not os.path.exists(path):
+        return None
+    steps, rec, es, ev = [], [], [], []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            f = line.strip().split(",")
+            if f[0] == "E":
+                es.append(int(f[1]))
+                ev.append(float(f[2]))
+            else:
+                steps.append(int(f[0]))
+                rec.append([float(x) for x in f[1:4]])
+    return {"steps": np.array(steps), "rec": np.array(rec),
+            "energy_steps": np.array(es), "energy": np.array(ev)}
+
+
+def run_paper(hw, torch, nsteps=60000):
+    """The acoustic experiment of Sec. 3: 600^2 (ppw 10), dt 1e-4, 60000
+    steps, Ricker point source on the pressure, one receiver; every storage
+    variant on the GPU against the FP64 oracle's receiver trace and energy,
+    plus fp32 at ppw 30 as the discretisation reference."""
+    import workloads
+    gold = read_paper_golden()
+    every = 500
+    out = {}
+
+    def one(w, storage, comp):
+        samples = w.source[2]
+        pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, w.order, storage, comp, w.dx,
+                        w.dt, 0, nsteps // every + 2, src_cap=len(samples),
+                        rec_cap=1, rec_steps=nsteps)
+        plan = hw.Plan(pb)
+        plan.set_material([w.rho, w.kappa])
+        plan.set_fields(w.fields())
+        plan.set_source(w.source[0], w.source[1], samples)
+        plan.set_receivers(w.receivers)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        plan.advance(nsteps, every)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        rec = plan.receiver_trace()[:, 0, :]
+        energy, esteps = plan.energy_trace()
+        plan.close()
+        return ms, rec, energy, esteps
+
+    w10 = workloads.paper2d(ppw=10, nsteps=nsteps)
+    src_end = len(w10.source[2])
+    for storage, comp in PAPER_VARIANTS:
+        ms, rec, energy, esteps = one(w10, storage, comp)
+        r = {"glups": w10.cells * nsteps / (ms * 1e-3) / 1e9, "ms_total": ms}
+        # energy change once the source has stopped injecting (Sec. 3: flat
+        # for a conserving run)
+        after = esteps >= src_end + every
+        e_after = energy[after]
+        r["energy_change_after_source"] = float((e_after[-1] - e_after[0]) / e_after[0])
+        if gold is not None:
+            idx = gold["steps"] - 1
+            p = rec[idx, 0]
+            ref = gold["rec"][:, 0]
+            r["p_trace_rel_l2_vs_fp64"] = float(np.linalg.norm(p - ref) / np.linalg.norm(ref))
+            ge = np.interp(esteps, gold["energy_steps"], gold["energy"])
+            m = esteps >= every
+            r["energy_max_rel_dev_vs_fp64"] = float(np.max(np.abs(energy[m] - ge[m]) / ge[m]))
+        out[f"{storage}+{comp}"] = r
+        print(f"# paper2d ppw10 {storage}+{comp}: {r}", file=sys.stderr, flush=True)
+    res = {"workload": "acoustic2d order-4 600x600 (ppw 10), dx 1/125, dt 1e-4, rho=c=1, "
+                       f"{nsteps} steps, Ricker 5 Hz point source at (200,200), "
+                       "receiver at (400,400) (Sec. 3)",
+           "reference": "FP64 oracle" if gold is not None else None,
+           "variants": out}
+    # discretisation reference: fp32 at ppw 30 (same physical positions)
+    w30 = workloads.paper2d(ppw=30, nsteps=nsteps)
+    ms, rec30, _, _ = one(w30, "f32", "none")
+    res["f32_ppw30_glups"] = w30.cells * nsteps / (ms * 1e-3) / 1e9
+    if gold is not None:
+        idx = gold["steps"] - 1
+        ref = gold["rec"][:, 0]
+        res["discretisation_rel_l2_ppw10_vs_ppw30"] = float(
+            np.linalg.norm(rec30[idx, 0] - ref) / np.linalg.norm(ref))
+    print(f"# paper2d ppw30 f32: {res.get('discretisation_rel_l2_ppw10_vs_ppw30')}",
+          file=sys.stderr, flush=True)
+    return res
+
+
 def run_serving(hw, torch, nreq, glups2d, glups3d, chunk=200):
     """Poisson stream of mixed requests (70% 2D order-4 512^2..4096^2, 30% 3D
     128^3..384^3, 1000..10000 steps, fp32 or fp16+TwoSum), arrival rate set so
@@ -301,9 +401,10 @@ def main():
     ap.add_argument("--elastic-steps", type=int, default=2000)
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--sections", default="2d,3d,batched,serving",
+    ap.add_argument("--sections", default="2d,3d,batched,serving,paper",
                     help="comma list of workloads to run: 2d (always reported), "
-                         "3d, batched, serving")
+                         "3d, batched, serving, paper (the Sec. 3 experiment)")
+    ap.add_argument("--paper-steps", type=int, default=60000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates "
                          "the HBM byte counters against a known size)")
@@ -374,6 +475,8 @@ def main():
     if "serving" in sections:
         g3 = extra["elastic3d"]["variants"]["f16+twosum"]["glups"]
         extra["serving"] = run_serving(hw, torch, args.requests, head["glups"], g3)
+    if "paper" in sections:
+        extra["paper2d"] = run_paper(hw, torch, args.paper_steps)
     f32 = results.get("f32+none")
     out = {
         "metric": METRIC,

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define HW_ABI_VERSION 2u
+#define HW_ABI_VERSION 3u
 
 typedef enum hw_status {
     HW_OK = 0,
@@ -87,6 +87,11 @@ typedef struct hw_problem {
     double dx;             /* grid spacing, all axes, > 0                     */
     double dt;             /* time step, > 0                                  */
     int64_t trace_cap;     /* energy samples reserved in the arena, >= 0      */
+    /* Point source and receivers (acoustic only; 0 for elastic): */
+    int64_t src_cap;       /* source samples reserved in the arena, >= 0      */
+    int32_t rec_cap;       /* receivers reserved, 0 .. 64                     */
+    int32_t reserved;      /* must be 0                                       */
+    int64_t rec_steps;     /* receiver trace rows reserved, >= 0              */
 } hw_problem;
 
 typedef struct hw_plan hw_plan;
@@ -167,6 +172,38 @@ hw_status hw_energy_trace(hw_plan *plan, double *energy, int64_t *step,
  * both in the field order.  NULL entries are skipped.  Synchronises. */
 hw_status hw_get_fields(hw_plan *plan, double *const *fields,
                         double *const *comps, void *stream);
+
+/* Point source on the pressure (the s_p term of Eq. 1, Sec. 3; the source
+ * line of Alg. 1/2).  In the plan's step n (advancing the state from step n
+ * to n+1, n counted from the last hw_set_fields or the imported step), the
+ * pressure right-hand side at cell (ix, iy) -- the sum of the two stencil
+ * terms -- gets samples[n] added before the multiplication by kappa, for
+ * 0 <= n < nsamples; the sample is rounded to fp32 like the rest of the
+ * stencil arithmetic.  samples: nsamples host fp64 values (already scaled
+ * by 2^scale_log2 if the plan uses a field scale).  nsamples = 0 removes the
+ * source.  A plan with a source or receivers steps with kernel shape 0
+ * whatever its hw_plan_set_tile setting (the shapes give identical bits).
+ * HW_E_INVAL for elastic plans or a cell outside the grid,
+ * HW_E_NOMEM if nsamples > src_cap.  Synchronises `stream` (the samples are
+ * copied before the call returns). */
+hw_status hw_set_source(hw_plan *plan, int64_t ix, int64_t iy,
+                        const double *samples, int64_t nsamples, void *stream);
+
+/* Receivers: after each step n < rec_steps the new pressure p^{n+1} and
+ * velocities vx^{n+1/2}, vy^{n+1/2} at each of the n cells (ix[r], iy[r])
+ * are recorded in fp64 (exact widening, unscaled); row n of the trace
+ * belongs to step n, counted as for hw_set_source.  0 <= n <= rec_cap
+ * (HW_E_NOMEM), cells inside the grid (HW_E_INVAL).  n = 0 removes the
+ * receivers.  Synchronises `stream`. */
+hw_status hw_set_receivers(hw_plan *plan, int32_t n, const int64_t *ix,
+                           const int64_t *iy, void *stream);
+
+/* Copy the receiver trace to the host: out[(k*n + r)*3 + {0, 1, 2}] =
+ * (p, vx, vy) of receiver r after step k, for k < min(cap_rows, rows), n the
+ * receiver count; *rows_out = rows recorded (min(step, rec_steps)).
+ * Synchronises `stream`. */
+hw_status hw_receiver_trace(hw_plan *plan, double *out, int64_t cap_rows,
+                            int64_t *rows_out, void *stream);
 
 /* Current step count of the plan. */
 int64_t hw_plan_step(const hw_plan *plan);

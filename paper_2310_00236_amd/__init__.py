@@ -29,7 +29,7 @@ ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
 STATUS = {0: "HW_OK", 1: "HW_E_INVAL", 2: "HW_E_UNSTABLE", 3: "HW_E_RANGE",
           4: "HW_E_NOMEM", 5: "HW_E_DEVICE", 6: "HW_E_NONFINITE",
           7: "HW_E_STATE"}
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class HalfwaveError(RuntimeError):
@@ -45,7 +45,9 @@ class _Problem(ctypes.Structure):
                 ("comp", ctypes.c_int32), ("scale_log2", ctypes.c_int32),
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("nz", ctypes.c_int64), ("dx", ctypes.c_double),
-                ("dt", ctypes.c_double), ("trace_cap", ctypes.c_int64)]
+                ("dt", ctypes.c_double), ("trace_cap", ctypes.c_int64),
+                ("src_cap", ctypes.c_int64), ("rec_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rec_steps", ctypes.c_int64)]
 
 
 _lib = None
@@ -96,6 +98,9 @@ def lib():
         "hw_tile_info": (I32, [I32, I32, ctypes.POINTER(I32), ctypes.POINTER(I32),
                                ctypes.POINTER(I32), ctypes.POINTER(I32)]),
         "hw_plan_set_tile": (I32, [PPlan, I32]),
+        "hw_set_source": (I32, [PPlan, I64, I64, PD, I64, P]),
+        "hw_set_receivers": (I32, [PPlan, I32, PI64, PI64, P]),
+        "hw_receiver_trace": (I32, [PPlan, PD, I64, PI64, P]),
         "hw_batch_advance": (I32, [ctypes.POINTER(P), I32, PI64, I64, I32, P]),
         "hw_simulate": (I32, [PProb, PPD, PPD, I64, I64, PD, I64, PI64, P,
                               ctypes.c_size_t, P]),
@@ -154,13 +159,17 @@ class Problem:
     dt: float = 0.5
     scale_log2: int = 0
     trace_cap: int = 0
+    src_cap: int = 0              # point-source samples reserved (acoustic)
+    rec_cap: int = 0              # receivers reserved (acoustic, <= 64)
+    rec_steps: int = 0            # receiver trace rows reserved
 
     def c(self) -> _Problem:
         return _Problem(ABI_VERSION,
                         {"acoustic2d": ACOUSTIC2D, "elastic3d": ELASTIC3D}[self.physics],
                         self.order, STORAGE[self.storage], COMP[self.comp],
                         self.scale_log2, self.nx, self.ny, self.nz, self.dx,
-                        self.dt, self.trace_cap)
+                        self.dt, self.trace_cap, self.src_cap, self.rec_cap, 0,
+                        self.rec_steps)
 
     @property
     def shape(self):
@@ -301,6 +310,35 @@ class Plan:
     def import_state(self, blob: bytes, stream=None):
         buf = ctypes.create_string_buffer(blob, len(blob))
         _check(lib().hw_state_import(self.handle, buf, len(blob), self._s(stream)))
+
+    def set_source(self, ix: int, iy: int, samples, stream=None):
+        """Point source on the pressure at cell (ix, iy); step n adds
+        samples[n] (see hw_set_source).  An empty sample list removes it."""
+        a = np.ascontiguousarray(np.asarray(samples, dtype=np.float64).ravel())
+        _check(lib().hw_set_source(self.handle, ix, iy,
+                                   a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   len(a), self._s(stream)))
+
+    def set_receivers(self, cells, stream=None):
+        """Record (p, vx, vy) at the given (ix, iy) cells after every step."""
+        cells = list(cells)
+        ix = np.ascontiguousarray([c[0] for c in cells] or [0], dtype=np.int64)
+        iy = np.ascontiguousarray([c[1] for c in cells] or [0], dtype=np.int64)
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        _check(lib().hw_set_receivers(self.handle, len(cells), ix.ctypes.data_as(P64),
+                                      iy.ctypes.data_as(P64), self._s(stream)))
+        self._nrec = len(cells)
+
+    def receiver_trace(self, stream=None) -> np.ndarray:
+        """[rows, receivers, 3] array of (p, vx, vy) after each step."""
+        nrec = getattr(self, "_nrec", 0)
+        rows = ctypes.c_int64()
+        cap = max(self.pb.rec_steps, 1)
+        out = np.zeros((cap, max(nrec, 1), 3))
+        _check(lib().hw_receiver_trace(self.handle,
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       cap, ctypes.byref(rows), self._s(stream)))
+        return out[:rows.value, :nrec].copy()
 
 
 def batch_advance(plans: Sequence[Plan], nsteps, energy_every: int = 0,

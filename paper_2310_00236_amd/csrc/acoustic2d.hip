@@ -173,6 +173,61 @@ __device__ __forceinline__ void update_one(typename Word<S, COMP>::type &w, floa
     w = WD::make(v, c);
 }
 
+// Point source and receivers of one plan in the current step (Sec. 3: the
+// s_p term of Eq. 1, and the receivers' time histories).  The plan's
+// device step counter tells which sample and which trace row this step
+// uses; it is read only when the plan has a source or receivers.
+struct Forcing {
+    bool src;        // the source is active in this step
+    float s;         // its sample (fp32)
+    int sx, sy;      // source cell
+    int rn;          // receivers recorded in this step (0: none)
+    int64_t row;     // their trace row
+};
+
+__device__ __forceinline__ Forcing forcing(const Ac2dDesc &d)
+{
+    Forcing f{false, 0.0f, d.src_x, d.src_y, 0, 0};
+    if (d.src_n > 0 || d.rec_n > 0) {
+        const int64_t n = *gmem(d.step);
+        if (n < d.src_n) {
+            f.src = true;
+            f.s = gmem(d.src)[n];
+        }
+        if (d.rec_n > 0 && n < d.rec_rows) {
+            f.rn = d.rec_n;
+            f.row = n;
+        }
+    }
+    return f;
+}
+
+// Record component c (0 p, 1 vx, 2 vy) of cell (x, y) if it is a receiver;
+// values are unscaled and widened to fp64 exactly.
+__device__ __forceinline__ void record(const Ac2dDesc &d, const Forcing &f, int c,
+                                       int x, int y, float v)
+{
+    const int32_t HW_GLOBAL *xy = gmem(d.rec_xy);
+    for (int r = 0; r < f.rn; ++r)
+        if (xy[2 * r] == x && xy[2 * r + 1] == y)
+            gmem(d.rec)[(f.row * f.rn + r) * 3 + c] = (double)v * d.rec_scale;
+}
+
+// One-thread kernels that advance the device step counters of the plans of
+// a launch (after their step) and set one counter.
+__global__ void tick_kernel(const StepCounters c)
+{
+    const int i = threadIdx.x;
+    if (i < c.n)
+        c.c[i][0] += 1;
+}
+
+__global__ void set_counter_kernel(int64_t *c, int64_t v)
+{
+    if (threadIdx.x == 0)
+        *c = v;
+}
+
 // A workgroup of 4 wavefronts owns a tile of TX = 64*V by TY cells.  Each
 // wavefront handles whole tile rows (row r goes to wavefront r mod 4) and
 // each lane V adjacent cells of a row, so every field of a lane's cells is
@@ -181,7 +236,7 @@ __device__ __forceinline__ void update_one(typename Word<S, COMP>::type &w, floa
 // row keeps the same wavefront and register slot in every region (a cell's
 // old pressure word, loaded with the pressure tile, is still in registers
 // when its update runs).
-template <class S, int COMP, int ORDER, int V, int TY, bool WX>
+template <class S, int COMP, int ORDER, int V, int TY, bool WX, bool FRC>
 __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                                           int y0, bool yin, float *ps, float *bs,
                                           float *vxs, float *vys)
@@ -214,6 +269,8 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     W HW_GLOBAL *__restrict__ vx_out = gmem((W *)d.vx[par ^ 1]);
     W HW_GLOBAL *__restrict__ vy_out = gmem((W *)d.vy[par ^ 1]);
     const int xl = V * ln;                    // first tile column of the lane
+    // point source and receivers: compiled in only for plans that have them
+    const Forcing fc = FRC ? forcing(d) : Forcing{false, 0.0f, 0, 0, 0, 0};
     auto grow = [&](int ly) { const int g = y0 + ly; return yin ? g : wrapi(g, ny); };
     auto gcol = [&](int lx) { const int g = x0 + lx; return WX ? wrapi(g, nx) : g; };
     // V adjacent words of one row starting at tile column xl
@@ -379,6 +436,12 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
 #pragma unroll
             for (int i = 0; i < V; ++i)
                 r[xl + i] = S::load(WD::v(vxw[k].w[i]));
+            if (fc.rn > 0) {
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                    if (x0 + xl + i < nx)
+                        record(d, fc, 1, x0 + xl + i, y0 + ly, S::load(WD::v(vxw[k].w[i])));
+            }
             W HW_GLOBAL *o = vx_out + (y0 + ly) * pitch + x0 + xl;
             if (!WX || x0 + TX <= nx) {
                 store_cells_nt<W, V>(o, vxw[k]);
@@ -422,6 +485,12 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
             for (int i = 0; i < V; ++i)
                 r[xl + i] = S::load(WD::v(vyw[k].w[i]));
             if (ly >= 0 && ly < TY && y0 + ly < ny) {
+                if (fc.rn > 0) {
+#pragma unroll
+                    for (int i = 0; i < V; ++i)
+                        if (x0 + xl + i < nx)
+                            record(d, fc, 2, x0 + xl + i, y0 + ly, S::load(WD::v(vyw[k].w[i])));
+                }
                 W HW_GLOBAL *o = vy_out + (y0 + ly) * pitch + x0 + xl;
                 if (!WX || x0 + TX <= nx) {
                     store_cells_nt<W, V>(o, vyw[k]);
@@ -458,11 +527,21 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                     gxv = w1 * ax0;
                     gyv = w1 * ay0;
                 }
-                const float dv = gxv + gyv;
+                float dv = gxv + gyv;
+                // point source: the sample joins the right-hand side
+                // before the scaling by kappa
+                if (fc.src && y0 + ly == fc.sy && x0 + xl + i == fc.sx)
+                    dv = dv + fc.s;
                 inc[i] = km[k][i] * dv;
             }
             CV &pc = pw[k + OP / 4];          // row ly's pressure words
             update_cells<S, COMP, V>(pc, inc);
+            if (fc.rn > 0) {
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                    if (x0 + xl + i < nx)
+                        record(d, fc, 0, x0 + xl + i, y0 + ly, S::load(WD::v(pc.w[i])));
+            }
             W HW_GLOBAL *o = p_out + (y0 + ly) * pitch + x0 + xl;
             if (!WX || x0 + TX <= nx) {
                 store_cells_nt<W, V>(o, pc);
@@ -748,7 +827,7 @@ struct TileLds {
     float vys[(TY + 2 * R - 1) * TX];        // new vy
 };
 
-template <class S, int COMP, int ORDER, int V, int TY>
+template <class S, int COMP, int ORDER, int V, int TY, bool FRC>
 __device__ __forceinline__ void ac2d_tile_entry(const Ac2dDesc &d, int par,
                                                 int tile, int ntx,
                                                 TileLds<S, COMP, ORDER, V, TY> &L)
@@ -762,27 +841,27 @@ __device__ __forceinline__ void ac2d_tile_entry(const Ac2dDesc &d, int par,
     const bool xin = x0 >= H && x0 + TX + H <= nx;
     const bool yin = y0 >= H && y0 + TY + H <= ny;
     if (xin)
-        ac2d_tile<S, COMP, ORDER, V, TY, false>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
+        ac2d_tile<S, COMP, ORDER, V, TY, false, FRC>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
     else
-        ac2d_tile<S, COMP, ORDER, V, TY, true>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
+        ac2d_tile<S, COMP, ORDER, V, TY, true, FRC>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
 }
 
-template <class S, int COMP, int ORDER, int V, int TY>
+template <class S, int COMP, int ORDER, int V, int TY, bool FRC = false>
 __global__ __launch_bounds__(kThreads) void ac2d_step_kernel(const Ac2dBatch a)
 {
     __shared__ TileLds<S, COMP, ORDER, V, TY> L;
     int32_t tile = xcd_tile(blockIdx.x, a.total_tiles);
     const int shot = find_shot(a, tile);
-    ac2d_tile_entry<S, COMP, ORDER, V, TY>(*a.desc[shot], a.parity[shot],
+    ac2d_tile_entry<S, COMP, ORDER, V, TY, FRC>(*a.desc[shot], a.parity[shot],
                                            tile - a.tile_start[shot],
                                            a.tiles_x[shot], L);
 }
 
-template <class S, int COMP, int ORDER, int V, int TY>
+template <class S, int COMP, int ORDER, int V, int TY, bool FRC = false>
 __global__ __launch_bounds__(kThreads) void ac2d_step1_kernel(const Ac2dOne o)
 {
     __shared__ TileLds<S, COMP, ORDER, V, TY> L;
-    ac2d_tile_entry<S, COMP, ORDER, V, TY>(o.d, o.parity,
+    ac2d_tile_entry<S, COMP, ORDER, V, TY, FRC>(o.d, o.parity,
                                            xcd_tile(blockIdx.x, o.total_tiles),
                                            o.tiles_x, L);
 }
@@ -870,7 +949,7 @@ __global__ __launch_bounds__(kThreads) void energy_finish_kernel(
 
 template <class S, int COMP, int ORDER>
 static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
-                            hipStream_t s)
+                            bool forced, hipStream_t s)
 {
     const dim3 grid(a.total_tiles), block(kThreads);
     Ac2dOne o;
@@ -879,6 +958,20 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
         o.parity = a.parity[0];
         o.tiles_x = a.tiles_x[0];
         o.total_tiles = a.total_tiles;
+    }
+    if (forced) {
+        // launches with a point source or receivers use tile shape 0
+        static_assert(kTiles2D[0].kind == 0 && kTiles2D[0].tx == 64, "tile 0");
+        if (tile != 0)
+            return hipErrorInvalidValue;
+        constexpr int T = kTiles2D[0].ty;
+        if (one)
+            hipLaunchKernelGGL((ac2d_step1_kernel<S, COMP, ORDER, 1, T, true>),
+                               grid, block, 0, s, o);
+        else
+            hipLaunchKernelGGL((ac2d_step_kernel<S, COMP, ORDER, 1, T, true>),
+                               grid, block, 0, s, a);
+        return hipGetLastError();
     }
     switch (tile) {
 #define HW_TILE(n)                                                                \
@@ -912,35 +1005,35 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
 
 template <class S, int COMP>
 static hipError_t step_order(const Ac2dBatch &a, const Ac2dDesc *one, int order,
-                             int tile, hipStream_t s)
+                             int tile, bool forced, hipStream_t s)
 {
-    return order == 4 ? step_tile<S, COMP, 4>(a, one, tile, s)
-                      : step_tile<S, COMP, 2>(a, one, tile, s);
+    return order == 4 ? step_tile<S, COMP, 4>(a, one, tile, forced, s)
+                      : step_tile<S, COMP, 2>(a, one, tile, forced, s);
 }
 
 template <class S>
 static hipError_t step_comp(const Ac2dBatch &a, const Ac2dDesc *one, int comp,
-                            int order, int tile, hipStream_t s)
+                            int order, int tile, bool forced, hipStream_t s)
 {
     switch (comp) {
-    case COMP_NONE: return step_order<S, COMP_NONE>(a, one, order, tile, s);
-    case COMP_FAST2SUM: return step_order<S, COMP_FAST2SUM>(a, one, order, tile, s);
-    case COMP_TWOSUM: return step_order<S, COMP_TWOSUM>(a, one, order, tile, s);
+    case COMP_NONE: return step_order<S, COMP_NONE>(a, one, order, tile, forced, s);
+    case COMP_FAST2SUM: return step_order<S, COMP_FAST2SUM>(a, one, order, tile, forced, s);
+    case COMP_TWOSUM: return step_order<S, COMP_TWOSUM>(a, one, order, tile, forced, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
-                            int comp, int order, int tile, hipStream_t s)
+                            int comp, int order, int tile, bool forced, hipStream_t s)
 {
     if (a.total_tiles <= 0)
         return hipSuccess;
     if (one && a.nshots != 1)
         return hipErrorInvalidValue;
     switch (storage) {
-    case HW_F32: return step_comp<F32>(a, one, comp, order, tile, s);
-    case HW_F16: return step_comp<F16>(a, one, comp, order, tile, s);
-    case HW_BF16: return step_comp<BF16>(a, one, comp, order, tile, s);
+    case HW_F32: return step_comp<F32>(a, one, comp, order, tile, forced, s);
+    case HW_F16: return step_comp<F16>(a, one, comp, order, tile, forced, s);
+    case HW_BF16: return step_comp<BF16>(a, one, comp, order, tile, forced, s);
     }
     return hipErrorInvalidValue;
 }
@@ -968,6 +1061,18 @@ hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity, int64_t ny,
     case HW_BF16: return energy_order<BF16>(d_desc, parity, ny, order, stride, partial, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_tick(const StepCounters &c, hipStream_t s)
+{
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(kMaxBatch), 0, s, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_counter(int64_t *c, int64_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_counter_kernel, dim3(1), dim3(64), 0, s, c, value);
+    return hipGetLastError();
 }
 
 hipError_t launch_energy_finish(const double *partial, int64_t n,

@@ -24,6 +24,16 @@ struct Ac2dDesc {
     const float *b;               // 1/rho at p points
     const float *k;               // kappa at p points
     void *vx[2], *vy[2], *p[2];   // field sets (storage words)
+    // point source and receivers (src_n == 0 and rec_n == 0 when unused)
+    const int64_t *step;          // device count of steps since the upload
+    const float *src;             // per-step source samples (fp32)
+    int64_t src_n;                // samples; step n < src_n adds src[n]
+    int32_t src_x, src_y;         // source cell
+    int32_t rec_n;                // receivers
+    const int32_t *rec_xy;        // receiver cells (x, y) pairs
+    double *rec;                  // trace [rec_rows][rec_n][3] (p, vx, vy)
+    int64_t rec_rows;
+    double rec_scale;             // 2^-scale_log2 (unscales the record)
 };
 
 // Device-resident description of one 3D elastic plan; same word layout.
@@ -87,8 +97,10 @@ constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
 // Launchers (one translation unit per physics).
 // one: the host copy of the descriptor when the launch covers a single plan
 // (it is then passed by value), else nullptr
+// forced: some plan of the launch has a point source or receivers; such
+// launches must use tile shape 0
 hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
-                            int comp, int order, int tile, hipStream_t s);
+                            int comp, int order, int tile, bool forced, hipStream_t s);
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
                               int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);
@@ -100,6 +112,11 @@ hipError_t launch_el3d_energy(const El3dDesc *d_desc, int parity, int64_t rows,
 hipError_t launch_energy_finish(const double *partial, int64_t n,
                                 double factor, double *out, int32_t *flag,
                                 hipStream_t s);
+// Advance the device step counters of n plans by one (n <= kMaxBatch);
+// set one counter to a value.
+struct StepCounters { int64_t *c[kMaxBatch]; int32_t n; };
+hipError_t launch_tick(const StepCounters &c, hipStream_t s);
+hipError_t launch_set_counter(int64_t *c, int64_t value, hipStream_t s);
 
 // Conversions between fp64 host-layout arrays and the device layouts:
 // storage element (r*pitch + i)*stride + offset holds host value r*nx + i.

@@ -35,6 +35,7 @@ hw_status fail(hw_status st, const std::string &msg)
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr int32_t kMaxReceivers = 64;
 constexpr int64_t kPitchAlign = 64;   // elements
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -73,6 +74,7 @@ struct Layout {
     size_t off_fld[2][9] = {};
     size_t off_mat[3] = {}, off_staging = 0, off_partial = 0, off_trace = 0;
     size_t off_flags = 0, off_desc = 0, total = 0;
+    size_t off_src = 0, off_recxy = 0, off_rec = 0;
 };
 
 hw_status validate(const hw_problem *pb)
@@ -104,6 +106,16 @@ hw_status validate(const hw_problem *pb)
         return fail(HW_E_INVAL, "dx and dt must be finite and > 0");
     if (pb->trace_cap < 0)
         return fail(HW_E_INVAL, "trace_cap must be >= 0");
+    if (pb->src_cap < 0 || pb->rec_cap < 0 || pb->rec_cap > kMaxReceivers ||
+        pb->rec_steps < 0 || pb->reserved != 0)
+        return fail(HW_E_INVAL, "src_cap, rec_steps must be >= 0, rec_cap in "
+                                "[0, 64], reserved 0");
+    if (pb->physics != HW_ACOUSTIC2D &&
+        (pb->src_cap != 0 || pb->rec_cap != 0 || pb->rec_steps != 0))
+        return fail(HW_E_INVAL, "sources and receivers are acoustic only");
+    if ((double)pb->src_cap > 0x1p40 ||
+        (double)pb->rec_steps * (double)pb->rec_cap > 0x1p36)
+        return fail(HW_E_INVAL, "source or receiver capacity too large");
     const float w = (float)(pb->dt / pb->dx);
     if (!std::isfinite(w) || w == 0.0f)
         return fail(HW_E_INVAL, "dt/dx does not fit fp32");
@@ -148,8 +160,14 @@ Layout make_layout(const hw_problem *pb)
     off += align_up((size_t)L.rows * 8, kAlign);
     L.off_trace = off;
     off += align_up((size_t)std::max<int64_t>(pb->trace_cap, 1) * 8, kAlign);
-    L.off_flags = off;
+    L.off_flags = off;             // status flag (int32) and step counter (int64 at +8)
     off += kAlign;
+    L.off_src = off;
+    off += align_up((size_t)pb->src_cap * 4, kAlign);
+    L.off_recxy = off;
+    off += align_up((size_t)pb->rec_cap * 8, kAlign);
+    L.off_rec = off;
+    off += align_up((size_t)pb->rec_steps * pb->rec_cap * 3 * 8, kAlign);
     L.off_desc = off;
     off += align_up(std::max(sizeof(Ac2dDesc), sizeof(El3dDesc)), kAlign);
     L.total = off;
@@ -186,6 +204,8 @@ struct hw_plan {
     bool have_material = false, have_fields = false;
     int tile = 0;
     double scale_up = 1.0, scale_down = 1.0;
+    int64_t *counter = nullptr;    // device step counter (sources, receivers)
+    bool counts() const { return h2.src_n > 0 || h2.rec_n > 0; }
     // captured run of kGraphSteps steps starting from field set 0
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -233,11 +253,16 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             Ac2dBatch a;
             std::memset(&a, 0, sizeof(a));
             a.nshots = m;
+            // plans with a point source or receivers run on tile shape 0
+            bool forced = false;
+            for (int i = 0; i < m; ++i)
+                forced = forced || plans[base + i]->counts();
+            const int t = forced ? 0 : tile;
             int64_t total = 0;
             for (int i = 0; i < m; ++i) {
                 hw_plan *p = plans[base + i];
                 int32_t tx, ty, tt;
-                tile_counts(p, tile, &tx, &ty, &tt);
+                tile_counts(p, t, &tx, &ty, &tt);
                 a.tile_start[i] = (int32_t)total;
                 a.tiles_x[i] = tx;
                 a.tiles_y[i] = ty;
@@ -250,7 +275,15 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             a.tile_start[m] = (int32_t)total;
             a.total_tiles = (int32_t)total;
             e = launch_ac2d_step(a, m == 1 ? &plans[base]->h2 : nullptr,
-                                 p0->pb.storage, p0->pb.comp, p0->pb.order, tile, s);
+                                 p0->pb.storage, p0->pb.comp, p0->pb.order, t, forced, s);
+            // plans with a source or receivers count their steps on the device
+            StepCounters c;
+            c.n = 0;
+            for (int i = 0; i < m; ++i)
+                if (plans[base + i]->counts())
+                    c.c[c.n++] = plans[base + i]->counter;
+            if (e == hipSuccess && c.n > 0)
+                e = launch_tick(c, s);
         } else {
             El3dBatch a;
             std::memset(&a, 0, sizeof(a));
@@ -675,6 +708,13 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
             d.vy[s] = p->fld[s][1];
             d.p[s] = p->fld[s][2];
         }
+        p->counter = (int64_t *)(p->arena + L.off_flags + 8);
+        d.step = p->counter;
+        d.src = (const float *)(p->arena + L.off_src);
+        d.rec_xy = (const int32_t *)(p->arena + L.off_recxy);
+        d.rec = (double *)(p->arena + L.off_rec);
+        d.rec_rows = pb->rec_steps;
+        d.rec_scale = p->scale_down;
     } else {
         El3dDesc &d = p->h3;
         std::memset(&d, 0, sizeof(d));
@@ -897,6 +937,8 @@ hw_status hw_state_import(hw_plan *p, const void *blob, size_t bytes, void *stre
         HW_HIP(hipMemcpyAsync(p->fld[0][f], src, p->L.field_bytes,
                               hipMemcpyHostToDevice, s));
     HW_HIP(launch_fill_zero(p->flags, kAlign, s));
+    if (p->counter)
+        HW_HIP(launch_set_counter(p->counter, h.step, s));
     HW_HIP(hipStreamSynchronize(s));
     p->cur = 0;
     p->step = h.step;
@@ -904,6 +946,96 @@ hw_status hw_state_import(hw_plan *p, const void *blob, size_t bytes, void *stre
     p->last_logged = -1;
     p->trace_steps.clear();
     p->have_fields = true;
+    return HW_OK;
+}
+
+hw_status hw_set_source(hw_plan *p, int64_t ix, int64_t iy, const double *samples,
+                        int64_t nsamples, void *stream)
+{
+    if (!p)
+        return fail(HW_E_INVAL, "plan is NULL");
+    if (p->pb.physics != HW_ACOUSTIC2D)
+        return fail(HW_E_INVAL, "sources are acoustic only");
+    if (nsamples < 0 || (nsamples > 0 && !samples))
+        return fail(HW_E_INVAL, "bad sample array");
+    if (nsamples > p->pb.src_cap)
+        return fail(HW_E_NOMEM, "more samples than src_cap");
+    if (nsamples > 0 && (ix < 0 || ix >= p->pb.nx || iy < 0 || iy >= p->pb.ny))
+        return fail(HW_E_INVAL, "source cell outside the grid");
+    std::vector<float> v((size_t)nsamples);
+    for (int64_t n = 0; n < nsamples; ++n) {
+        if (!std::isfinite(samples[n]) || !std::isfinite((float)samples[n]))
+            return fail(HW_E_RANGE, "source sample not finite in fp32");
+        v[(size_t)n] = (float)samples[n];     // round to nearest even
+    }
+    hipStream_t s = S(stream);
+    HW_HIP(hipStreamSynchronize(s));
+    if (nsamples > 0)
+        HW_HIP(hipMemcpy((void *)p->h2.src, v.data(), v.size() * 4,
+                         hipMemcpyHostToDevice));
+    p->h2.src_n = nsamples;
+    p->h2.src_x = (int32_t)(nsamples > 0 ? ix : 0);
+    p->h2.src_y = (int32_t)(nsamples > 0 ? iy : 0);
+    hw_status st = upload_desc(p, s);
+    if (st == HW_OK && p->graph) {      // the captured launches hold the old descriptor
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    if (st == HW_OK)
+        HW_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+hw_status hw_set_receivers(hw_plan *p, int32_t n, const int64_t *ix, const int64_t *iy,
+                           void *stream)
+{
+    if (!p)
+        return fail(HW_E_INVAL, "plan is NULL");
+    if (p->pb.physics != HW_ACOUSTIC2D)
+        return fail(HW_E_INVAL, "receivers are acoustic only");
+    if (n < 0 || (n > 0 && (!ix || !iy)))
+        return fail(HW_E_INVAL, "bad receiver arrays");
+    if (n > p->pb.rec_cap)
+        return fail(HW_E_NOMEM, "more receivers than rec_cap");
+    std::vector<int32_t> xy((size_t)n * 2);
+    for (int32_t r = 0; r < n; ++r) {
+        if (ix[r] < 0 || ix[r] >= p->pb.nx || iy[r] < 0 || iy[r] >= p->pb.ny)
+            return fail(HW_E_INVAL, "receiver cell outside the grid");
+        xy[2 * (size_t)r] = (int32_t)ix[r];
+        xy[2 * (size_t)r + 1] = (int32_t)iy[r];
+    }
+    hipStream_t s = S(stream);
+    HW_HIP(hipStreamSynchronize(s));
+    if (n > 0)
+        HW_HIP(hipMemcpy((void *)p->h2.rec_xy, xy.data(), xy.size() * 4,
+                         hipMemcpyHostToDevice));
+    p->h2.rec_n = n;
+    hw_status st = upload_desc(p, s);
+    if (st == HW_OK && p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    if (st == HW_OK)
+        HW_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+hw_status hw_receiver_trace(hw_plan *p, double *out, int64_t cap_rows, int64_t *rows_out,
+                            void *stream)
+{
+    if (!p)
+        return fail(HW_E_INVAL, "plan is NULL");
+    if (p->pb.physics != HW_ACOUSTIC2D)
+        return fail(HW_E_INVAL, "receivers are acoustic only");
+    const int64_t rows = std::min(p->step, p->pb.rec_steps);
+    if (rows_out)
+        *rows_out = rows;
+    hipStream_t s = S(stream);
+    const int64_t k = std::min(rows, std::max<int64_t>(cap_rows, 0));
+    if (out && k > 0 && p->h2.rec_n > 0)
+        HW_HIP(hipMemcpyAsync(out, p->h2.rec, (size_t)k * p->h2.rec_n * 3 * 8,
+                              hipMemcpyDeviceToHost, s));
+    HW_HIP(hipStreamSynchronize(s));
     return HW_OK;
 }
 

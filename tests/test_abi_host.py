@@ -67,6 +67,9 @@ def _pb(**kw):
     dict(nx=0), dict(ny=-1), dict(nz=2), dict(order=3), dict(order=6),
     dict(physics="elastic3d", nz=4, order=4), dict(dt=0.0), dict(dx=-1.0),
     dict(dt=float("nan")), dict(trace_cap=-1), dict(scale_log2=61),
+    dict(src_cap=-1), dict(rec_cap=65), dict(rec_cap=-1), dict(rec_steps=-2),
+    dict(physics="elastic3d", nz=4, order=2, src_cap=8),
+    dict(physics="elastic3d", nz=4, order=2, rec_cap=1, rec_steps=4),
 ])
 def test_invalid_problems(kw):
     with pytest.raises(hw.HalfwaveError) as ei:
@@ -176,3 +179,38 @@ def test_advance_before_upload_is_state_error():
     assert hw.lib().hw_advance(h, 1, 0, None) == 7
     assert hw.lib().hw_plan_step(h) == 0
     hw.lib().hw_plan_destroy(h)
+
+
+def test_footprint_reserves_source_and_receivers():
+    base = hw.footprint(_pb())
+    assert hw.footprint(_pb(src_cap=1000)) >= base + 4000
+    assert hw.footprint(_pb(rec_cap=3, rec_steps=100)) >= base + 3 * 100 * 3 * 8
+
+
+def test_source_and_receiver_validation_before_device():
+    """Every argument check of hw_set_source / hw_set_receivers runs before
+    any HIP call, so a plan on a placeholder arena exercises them all."""
+    P = ctypes.POINTER(ctypes.c_double)
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    st, h = _plan(_pb(src_cap=4, rec_cap=2, rec_steps=10))
+    assert st == 0
+    L = hw.lib()
+    s5 = np.ones(5)
+    assert L.hw_set_source(h, 1, 1, s5.ctypes.data_as(P), 5, None) == 4   # > src_cap
+    assert L.hw_set_source(h, 32, 1, s5.ctypes.data_as(P), 4, None) == 1  # x outside
+    assert L.hw_set_source(h, 0, -1, s5.ctypes.data_as(P), 4, None) == 1
+    bad = np.array([1.0, np.inf, 0.0, 0.0])
+    assert L.hw_set_source(h, 0, 0, bad.ctypes.data_as(P), 4, None) == 3  # RANGE
+    big = np.array([1e39, 0.0, 0.0, 0.0])                                  # fp32 overflow
+    assert L.hw_set_source(h, 0, 0, big.ctypes.data_as(P), 4, None) == 3
+    ix = np.array([0, 5, 7], dtype=np.int64)
+    iy = np.array([0, 23, 24], dtype=np.int64)
+    assert L.hw_set_receivers(h, 3, ix.ctypes.data_as(P64), iy.ctypes.data_as(P64), None) == 4
+    assert L.hw_set_receivers(h, 2, ix[1:].ctypes.data_as(P64), iy[1:].ctypes.data_as(P64),
+                              None) == 1                                  # y = 24 outside
+    L.hw_plan_destroy(h)
+    st, h = _plan(_pb(physics="elastic3d", nz=4, order=2))
+    assert st == 0
+    assert L.hw_set_source(h, 0, 0, s5.ctypes.data_as(P), 1, None) == 1
+    assert L.hw_set_receivers(h, 1, ix.ctypes.data_as(P64), iy.ctypes.data_as(P64), None) == 1
+    L.hw_plan_destroy(h)
