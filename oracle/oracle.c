@@ -239,19 +239,31 @@ typedef struct {
 
 #define IX(j, i) (wrap((j), G->ny) * G->nx + wrap((i), G->nx))
 
+/* Coefficients of the step in the stencil format sf: the fp32 values,
+ * rounded once more when the stencil runs in a format narrower than fp32
+ * (the all-fp16 / all-bf16 step of Alg. 1 taken literally: weights and
+ * material are then values of that format as well). */
+static double narrow(double x, int sf)
+{
+    return (sf == FMT_F16 || sf == FMT_BF16) ? orc_round(x, sf) : x;
+}
+
 static void ac2d_setup(ac2d *G, long nx, long ny, int order, double dx,
-                       double dt, const double *rho, const double *kappa)
+                       double dt, const double *rho, const double *kappa,
+                       int sf)
 {
     G->nx = nx;
     G->ny = ny;
     G->order = order;
     weights(order, dt, dx, &G->w1, &G->w2);
+    G->w1 = narrow(G->w1, sf);
+    G->w2 = narrow(G->w2, sf);
     long n = nx * ny;
     G->b = malloc(sizeof(double) * n);
     G->k = malloc(sizeof(double) * n);
     for (long i = 0; i < n; ++i) {
-        G->b[i] = f32v(1.0 / rho[i]);
-        G->k[i] = f32v(kappa[i]);
+        G->b[i] = narrow(f32v(1.0 / rho[i]), sf);
+        G->k[i] = narrow(f32v(kappa[i]), sf);
     }
 }
 
@@ -431,12 +443,13 @@ int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
         if (rec_x[r] < 0 || rec_x[r] >= nx || rec_y[r] < 0 || rec_y[r] >= ny)
             return -1;
     set_threads(nthreads);
-    ac2d G;
-    ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa);
+    ac2d G, GE;   /* the step's coefficients; the energy's (fp32 values) */
+    ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa, stencil);
+    ac2d_setup(&GE, nx, ny, order, dx, dt, rho, kappa, FMT_F32);
     arith A = {stencil, storage, comp};
     long m = 0;
     if (energy_every > 0)
-        energy[m++] = ac2d_energy(&G, dx, vx, vy, p);
+        energy[m++] = ac2d_energy(&GE, dx, vx, vy, p);
     for (long n = 1; n <= nsteps; ++n) {
         const long src_q = n - 1 < nsrc ? src_y * nx + src_x : -1;
         ac2d_step(&G, &A, vx, vy, p, cvx, cvy, cp, src_q,
@@ -449,9 +462,10 @@ int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
             o[2] = vy[q];
         }
         if (energy_every > 0 && n % energy_every == 0)
-            energy[m++] = ac2d_energy(&G, dx, vx, vy, p);
+            energy[m++] = ac2d_energy(&GE, dx, vx, vy, p);
     }
     ac2d_free(&G);
+    ac2d_free(&GE);
     return 0;
 }
 
@@ -461,7 +475,7 @@ double orc_acoustic2d_energy(long nx, long ny, int order, double dx,
                              const double *vy, const double *p)
 {
     ac2d G;
-    ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa);
+    ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa, FMT_F32);
     double e = ac2d_energy(&G, dx, vx, vy, p);
     ac2d_free(&G);
     return e;
