@@ -47,7 +47,7 @@ VARIANTS = [("f16", "twosum"), ("f32", "none"), ("f16", "none"), ("bf16", "none"
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for name in ("acoustic2d.hip", "hw_device.h", "hw_internal.h"):
+    for name in ("acoustic2d.hip", "acoustic2d_kernels.h", "hw_device.h", "hw_internal.h"):
         with open(os.path.join(ROOT, "paper_2310_00236_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -247,8 +247,13 @@ def run_batched(hw, torch, nshots):
 
 PAPER_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
                             "golden", "paper2d_ppw10_fp64.csv")
-PAPER_VARIANTS = [("f32", "none"), ("f16", "none"), ("f16", "fast2sum"),
-                  ("f16", "twosum"), ("bf16", "none"), ("bf16", "twosum")]
+PAPER_VARIANTS = [("f32", "none", "f32"), ("f16", "none", "f32"),
+                  ("f16", "fast2sum", "f32"), ("f16", "twosum", "f32"),
+                  ("bf16", "none", "f32"), ("bf16", "twosum", "f32"),
+                  # App. B: stencil promoted to fp64, update in fp16; and the
+                  # all-fp16 step of Alg. 1 taken literally
+                  ("f16", "none", "f64"), ("f16", "fast2sum", "f64"),
+                  ("f16", "none", "storage"), ("f16", "fast2sum", "storage")]
 
 
 def read_paper_golden(path=PAPER_GOLDEN):
@@ -282,11 +287,11 @@ def run_paper(hw, torch, nsteps=60000):
     every = 500
     out = {}
 
-    def one(w, storage, comp):
+    def one(w, storage, comp, stencil="f32"):
         samples = w.source[2]
         pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, w.order, storage, comp, w.dx,
                         w.dt, 0, nsteps // every + 2, src_cap=len(samples),
-                        rec_cap=1, rec_steps=nsteps)
+                        rec_cap=1, rec_steps=nsteps, stencil=stencil)
         plan = hw.Plan(pb)
         plan.set_material([w.rho, w.kappa])
         plan.set_fields(w.fields())
@@ -308,8 +313,8 @@ def run_paper(hw, torch, nsteps=60000):
 
     w10 = workloads.paper2d(ppw=10, nsteps=nsteps)
     src_end = len(w10.source[2])
-    for storage, comp in PAPER_VARIANTS:
-        ms, rec, energy, esteps = one(w10, storage, comp)
+    for storage, comp, stencil in PAPER_VARIANTS:
+        ms, rec, energy, esteps = one(w10, storage, comp, stencil)
         r = {"glups": w10.cells * nsteps / (ms * 1e-3) / 1e9, "ms_total": ms}
         # energy change once the source has stopped injecting (Sec. 3: flat
         # for a conserving run)
@@ -324,8 +329,9 @@ def run_paper(hw, torch, nsteps=60000):
             ge = np.interp(esteps, gold["energy_steps"], gold["energy"])
             m = esteps >= every
             r["energy_max_rel_dev_vs_fp64"] = float(np.max(np.abs(energy[m] - ge[m]) / ge[m]))
-        out[f"{storage}+{comp}"] = r
-        print(f"# paper2d ppw10 {storage}+{comp}: {r}", file=sys.stderr, flush=True)
+        key = f"{storage}+{comp}" + ("" if stencil == "f32" else f"/stencil-{stencil}")
+        out[key] = r
+        print(f"# paper2d ppw10 {key}: {r}", file=sys.stderr, flush=True)
     res = {"workload": "acoustic2d order-4 600x600 (ppw 10), dx 1/125, dt 1e-4, rho=c=1, "
                        f"{nsteps} steps, Ricker 5 Hz point source at (200,200), "
                        "receiver at (400,400) (Sec. 3)",

@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define HW_ABI_VERSION 3u
+#define HW_ABI_VERSION 4u
 
 typedef enum hw_status {
     HW_OK = 0,
@@ -73,6 +73,16 @@ typedef enum hw_status {
 enum hw_physics { HW_ACOUSTIC2D = 0, HW_ELASTIC3D = 1 };
 enum hw_storage { HW_F32 = 0, HW_F16 = 1, HW_BF16 = 2 };
 enum hw_comp { HW_COMP_NONE = 0, HW_COMP_FAST2SUM = 1, HW_COMP_TWOSUM = 2 };
+/* Precision of the stencil arithmetic (spatial differences, staggered
+ * material, scaling by the material); the solution update is always in the
+ * storage format.  HW_STENCIL_F32, the default, computes in fp32 from the
+ * stored values.  HW_STENCIL_STORAGE computes every operation in the storage
+ * format with the weights and the material rounded to it first (the
+ * all-fp16 step of Alg. 1 read literally).  HW_STENCIL_F64 computes in fp64
+ * from the stored values and the fp32 weights and material, rounding the
+ * increment once into the storage format (the promoted stencil of App. B).
+ * Non-default stencils are acoustic only. */
+enum hw_stencil { HW_STENCIL_F32 = 0, HW_STENCIL_STORAGE = 1, HW_STENCIL_F64 = 2 };
 
 typedef struct hw_problem {
     uint32_t abi_version;  /* must be HW_ABI_VERSION                          */
@@ -90,7 +100,7 @@ typedef struct hw_problem {
     /* Point source and receivers (acoustic only; 0 for elastic): */
     int64_t src_cap;       /* source samples reserved in the arena, >= 0      */
     int32_t rec_cap;       /* receivers reserved, 0 .. 64                     */
-    int32_t reserved;      /* must be 0                                       */
+    int32_t stencil;       /* enum hw_stencil (acoustic only; 0 for elastic)  */
     int64_t rec_steps;     /* receiver trace rows reserved, >= 0              */
 } hw_problem;
 
@@ -181,8 +191,11 @@ hw_status hw_get_fields(hw_plan *plan, double *const *fields,
  * 0 <= n < nsamples; the sample is rounded to fp32 like the rest of the
  * stencil arithmetic.  samples: nsamples host fp64 values (already scaled
  * by 2^scale_log2 if the plan uses a field scale).  nsamples = 0 removes the
- * source.  A plan with a source or receivers steps with kernel shape 0
- * whatever its hw_plan_set_tile setting (the shapes give identical bits).
+ * source.  The sample is rounded to fp32 on the host (and to the storage
+ * format inside the step when the plan's stencil is HW_STENCIL_STORAGE).
+ * A plan with a source, receivers or a non-default stencil steps with
+ * kernel shape 0 whatever its hw_plan_set_tile setting (the shapes give
+ * identical bits).
  * HW_E_INVAL for elastic plans or a cell outside the grid,
  * HW_E_NOMEM if nsamples > src_cap.  Synchronises `stream` (the samples are
  * copied before the call returns). */

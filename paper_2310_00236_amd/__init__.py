@@ -24,12 +24,13 @@ LIB_PATH = os.path.join(_HERE, "libhalfwave.so")
 ACOUSTIC2D, ELASTIC3D = 0, 1
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 COMP = {"none": 0, "fast2sum": 1, "twosum": 2}
+STENCIL = {"f32": 0, "storage": 1, "f64": 2}
 ACOUSTIC_FIELDS = ("vx", "vy", "p")
 ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
 STATUS = {0: "HW_OK", 1: "HW_E_INVAL", 2: "HW_E_UNSTABLE", 3: "HW_E_RANGE",
           4: "HW_E_NOMEM", 5: "HW_E_DEVICE", 6: "HW_E_NONFINITE",
           7: "HW_E_STATE"}
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class HalfwaveError(RuntimeError):
@@ -47,7 +48,7 @@ class _Problem(ctypes.Structure):
                 ("nz", ctypes.c_int64), ("dx", ctypes.c_double),
                 ("dt", ctypes.c_double), ("trace_cap", ctypes.c_int64),
                 ("src_cap", ctypes.c_int64), ("rec_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("rec_steps", ctypes.c_int64)]
+                ("stencil", ctypes.c_int32), ("rec_steps", ctypes.c_int64)]
 
 
 _lib = None
@@ -162,14 +163,15 @@ class Problem:
     src_cap: int = 0              # point-source samples reserved (acoustic)
     rec_cap: int = 0              # receivers reserved (acoustic, <= 64)
     rec_steps: int = 0            # receiver trace rows reserved
+    stencil: str = "f32"          # stencil precision: 'f32', 'storage', 'f64'
 
     def c(self) -> _Problem:
         return _Problem(ABI_VERSION,
                         {"acoustic2d": ACOUSTIC2D, "elastic3d": ELASTIC3D}[self.physics],
                         self.order, STORAGE[self.storage], COMP[self.comp],
                         self.scale_log2, self.nx, self.ny, self.nz, self.dx,
-                        self.dt, self.trace_cap, self.src_cap, self.rec_cap, 0,
-                        self.rec_steps)
+                        self.dt, self.trace_cap, self.src_cap, self.rec_cap,
+                        STENCIL[self.stencil], self.rec_steps)
 
     @property
     def shape(self):

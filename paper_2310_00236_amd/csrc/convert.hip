@@ -8,56 +8,6 @@
 
 namespace hw {
 
-// Round a double to the nearest value with `prec` significand bits and
-// smallest normal exponent `emin` (subnormal spacing 2^(emin-prec+1)), ties
-// to even, by integer arithmetic on the binary64 encoding.  Results beyond
-// maxfin become infinity.  The result is exactly representable in fp32.
-__device__ double round_double(double x, int prec, int emin, double maxfin)
-{
-    const uint64_t u = (uint64_t)__double_as_longlong(x);
-    const uint64_t sign = u & 0x8000000000000000ull;
-    const uint64_t mag = u ^ sign;
-    if (mag >= 0x7ff0000000000000ull || mag == 0)
-        return x;                                   // inf, nan, zero
-    const int ebits = (int)(mag >> 52);
-    if (ebits == 0)                                 // below 2^-1022: tiny
-        return __longlong_as_double((long long)sign);
-    const int e = ebits - 1023;                     // exponent of leading bit
-    const uint64_t m = (mag & 0x000fffffffffffffull) | 0x0010000000000000ull;
-    const int lead = e < emin ? emin : e;
-    // value = m * 2^(e-52); quantum = 2^(lead-prec+1); drop the low bits
-    const int drop = 52 - (prec - 1) + (lead - e);
-    if (drop > 60)
-        return __longlong_as_double((long long)sign);
-    uint64_t kept = m >> drop;
-    const uint64_t rem = m & ((1ull << drop) - 1);
-    const uint64_t half = 1ull << (drop - 1);
-    if (rem > half || (rem == half && (kept & 1)))
-        ++kept;
-    double r = ldexp((double)kept, lead - prec + 1);
-    if (r > maxfin)
-        r = __longlong_as_double(0x7ff0000000000000ll);
-    return sign ? -r : r;
-}
-
-template <class S>
-__device__ __forceinline__ typename S::store_t from_double(double x);
-template <>
-__device__ __forceinline__ float from_double<F32>(double x)
-{
-    return (float)x;   // fp64 -> fp32 conversion rounds to nearest even
-}
-template <>
-__device__ __forceinline__ _Float16 from_double<F16>(double x)
-{
-    return F16::store((float)round_double(x, 11, -14, 65504.0));
-}
-template <>
-__device__ __forceinline__ uint16_t from_double<BF16>(double x)
-{
-    return BF16::store((float)round_double(x, 8, -126, 0x1.fep127));
-}
-
 template <class S>
 __global__ __launch_bounds__(kThreads) void to_storage_kernel(
     const double *__restrict__ src, typename S::store_t *__restrict__ dst,

@@ -149,6 +149,98 @@ __device__ __forceinline__ void update_store(typename S::store_t &v,
     }
 }
 
+// Round a double to the nearest value with `prec` significand bits and
+// smallest normal exponent `emin` (subnormal spacing 2^(emin-prec+1)), ties
+// to even, by integer arithmetic on the binary64 encoding (a double to
+// float to half conversion would round twice).  Results beyond maxfin become
+// infinity.  The result is exactly representable in fp32.
+__device__ inline double round_double(double x, int prec, int emin, double maxfin)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint64_t sign = u & 0x8000000000000000ull;
+    const uint64_t mag = u ^ sign;
+    if (mag >= 0x7ff0000000000000ull || mag == 0)
+        return x;                                   // inf, nan, zero
+    const int ebits = (int)(mag >> 52);
+    if (ebits == 0)                                 // below 2^-1022: tiny
+        return __longlong_as_double((long long)sign);
+    const int e = ebits - 1023;                     // exponent of leading bit
+    const uint64_t m = (mag & 0x000fffffffffffffull) | 0x0010000000000000ull;
+    const int lead = e < emin ? emin : e;
+    // value = m * 2^(e-52); quantum = 2^(lead-prec+1); drop the low bits
+    const int drop = 52 - (prec - 1) + (lead - e);
+    if (drop > 60)
+        return __longlong_as_double((long long)sign);
+    uint64_t kept = m >> drop;
+    const uint64_t rem = m & ((1ull << drop) - 1);
+    const uint64_t half = 1ull << (drop - 1);
+    if (rem > half || (rem == half && (kept & 1)))
+        ++kept;
+    double r = ldexp((double)kept, lead - prec + 1);
+    if (r > maxfin)
+        r = __longlong_as_double(0x7ff0000000000000ll);
+    return sign ? -r : r;
+}
+
+// A double rounded once to the storage format.
+template <class S>
+__device__ __forceinline__ typename S::store_t from_double(double x);
+template <>
+__device__ __forceinline__ float from_double<F32>(double x)
+{
+    return (float)x;   // fp64 -> fp32 conversion rounds to nearest even
+}
+template <>
+__device__ __forceinline__ _Float16 from_double<F16>(double x)
+{
+    return F16::store((float)round_double(x, 11, -14, 65504.0));
+}
+template <>
+__device__ __forceinline__ uint16_t from_double<BF16>(double x)
+{
+    return BF16::store((float)round_double(x, 8, -126, 0x1.fep127));
+}
+
+// The updates with an fp64 increment (the stencil evaluated in fp64): the
+// increment, or increment plus compensation, is rounded once to the storage
+// format; the sum that follows is the same as above.
+template <class S, int COMP>
+__device__ __forceinline__ void update_store_d(typename S::store_t &v,
+                                               typename S::store_t &c, double inc)
+{
+    using T = typename S::store_t;
+    const T y = COMP == COMP_NONE ? from_double<S>(inc)
+                                  : from_double<S>(inc + (double)S::load(c));
+    if constexpr (S::id == F16::id) {
+        const _Float16 s = v + y;
+        if constexpr (COMP == COMP_FAST2SUM) {
+            const _Float16 z = s - v;
+            c = y - z;
+        } else if constexpr (COMP == COMP_TWOSUM) {
+            const _Float16 pa = s - y;
+            const _Float16 pb = s - pa;
+            const _Float16 da = v - pa;
+            const _Float16 db = y - pb;
+            c = da + db;
+        }
+        v = s;
+    } else {
+        const float vf = S::load(v), yf = S::load(y);
+        const float s = S::rn(vf + yf);
+        if constexpr (COMP == COMP_FAST2SUM) {
+            const float z = S::rn(s - vf);
+            c = S::store(S::rn(yf - z));
+        } else if constexpr (COMP == COMP_TWOSUM) {
+            const float pa = S::rn(s - yf);
+            const float pb = S::rn(s - pa);
+            const float da = S::rn(vf - pa);
+            const float db = S::rn(yf - pb);
+            c = S::store(S::rn(da + db));
+        }
+        v = S::store(s);
+    }
+}
+
 // Memory word of one field at one cell: the value alone, or the value and
 // its compensation term side by side.
 template <class S, int COMP>

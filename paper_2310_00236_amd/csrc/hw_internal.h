@@ -97,10 +97,17 @@ constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
 // Launchers (one translation unit per physics).
 // one: the host copy of the descriptor when the launch covers a single plan
 // (it is then passed by value), else nullptr
-// forced: some plan of the launch has a point source or receivers; such
-// launches must use tile shape 0
+// forced: some plan of the launch has a point source or receivers;
+// stencil: the stencil precision of the launch's plans (enum hw_stencil).
+// Forced launches and those with a non-default stencil use tile shape 0.
 hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
-                            int comp, int order, int tile, bool forced, hipStream_t s);
+                            int comp, int order, int tile, bool forced, int stencil,
+                            hipStream_t s);
+// The kernel variants with a point source, receivers and stencil
+// precisions (tile shape 0); format is the storage format's id (F32::id ...).
+hipError_t launch_ac2d_variant(const Ac2dBatch &a, const Ac2dDesc *one, int format,
+                               int comp, int order, int tile, int stencil,
+                               hipStream_t s);
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
                               int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);

@@ -107,12 +107,16 @@ hw_status validate(const hw_problem *pb)
     if (pb->trace_cap < 0)
         return fail(HW_E_INVAL, "trace_cap must be >= 0");
     if (pb->src_cap < 0 || pb->rec_cap < 0 || pb->rec_cap > kMaxReceivers ||
-        pb->rec_steps < 0 || pb->reserved != 0)
+        pb->rec_steps < 0)
         return fail(HW_E_INVAL, "src_cap, rec_steps must be >= 0, rec_cap in "
-                                "[0, 64], reserved 0");
+                                "[0, 64]");
+    if (pb->stencil < HW_STENCIL_F32 || pb->stencil > HW_STENCIL_F64)
+        return fail(HW_E_INVAL, "unknown stencil precision");
     if (pb->physics != HW_ACOUSTIC2D &&
-        (pb->src_cap != 0 || pb->rec_cap != 0 || pb->rec_steps != 0))
-        return fail(HW_E_INVAL, "sources and receivers are acoustic only");
+        (pb->src_cap != 0 || pb->rec_cap != 0 || pb->rec_steps != 0 ||
+         pb->stencil != HW_STENCIL_F32))
+        return fail(HW_E_INVAL, "sources, receivers and stencil precisions "
+                                "are acoustic only");
     if ((double)pb->src_cap > 0x1p40 ||
         (double)pb->rec_steps * (double)pb->rec_cap > 0x1p36)
         return fail(HW_E_INVAL, "source or receiver capacity too large");
@@ -175,11 +179,11 @@ Layout make_layout(const hw_problem *pb)
 }
 
 struct KernelKey {
-    int physics, order, storage, comp;
+    int physics, order, storage, comp, stencil;
     bool operator<(const KernelKey &o) const
     {
-        return std::tie(physics, order, storage, comp) <
-               std::tie(o.physics, o.order, o.storage, o.comp);
+        return std::tie(physics, order, storage, comp, stencil) <
+               std::tie(o.physics, o.order, o.storage, o.comp, o.stencil);
     }
 };
 
@@ -210,7 +214,7 @@ struct hw_plan {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_tile = -1;
-    KernelKey key() const { return {pb.physics, pb.order, pb.storage, pb.comp}; }
+    KernelKey key() const { return {pb.physics, pb.order, pb.storage, pb.comp, pb.stencil}; }
     ~hw_plan()
     {
         if (graph)
@@ -257,7 +261,8 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             bool forced = false;
             for (int i = 0; i < m; ++i)
                 forced = forced || plans[base + i]->counts();
-            const int t = forced ? 0 : tile;
+            const int stencil = p0->pb.stencil;
+            const int t = forced || stencil != HW_STENCIL_F32 ? 0 : tile;
             int64_t total = 0;
             for (int i = 0; i < m; ++i) {
                 hw_plan *p = plans[base + i];
@@ -275,7 +280,8 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             a.tile_start[m] = (int32_t)total;
             a.total_tiles = (int32_t)total;
             e = launch_ac2d_step(a, m == 1 ? &plans[base]->h2 : nullptr,
-                                 p0->pb.storage, p0->pb.comp, p0->pb.order, t, forced, s);
+                                 p0->pb.storage, p0->pb.comp, p0->pb.order, t, forced,
+                                 stencil, s);
             // plans with a source or receivers count their steps on the device
             StepCounters c;
             c.n = 0;

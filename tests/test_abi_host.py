@@ -70,6 +70,7 @@ def _pb(**kw):
     dict(src_cap=-1), dict(rec_cap=65), dict(rec_cap=-1), dict(rec_steps=-2),
     dict(physics="elastic3d", nz=4, order=2, src_cap=8),
     dict(physics="elastic3d", nz=4, order=2, rec_cap=1, rec_steps=4),
+    dict(physics="elastic3d", nz=4, order=2, stencil="f64"),
 ])
 def test_invalid_problems(kw):
     with pytest.raises(hw.HalfwaveError) as ei:
@@ -79,7 +80,7 @@ def test_invalid_problems(kw):
 
 def test_invalid_enums_and_abi():
     for field, val in (("storage", 7), ("comp", 5), ("physics", 3),
-                       ("abi_version", 99)):
+                       ("abi_version", 99), ("stencil", 3), ("stencil", -1)):
         c = _pb().c()
         setattr(c, field, val)
         n = ctypes.c_size_t()
