@@ -261,6 +261,7 @@ static void ac2d_setup(ac2d *G, long nx, long ny, int order, double dx,
     long n = nx * ny;
     G->b = malloc(sizeof(double) * n);
     G->k = malloc(sizeof(double) * n);
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
         G->b[i] = narrow(f32v(1.0 / rho[i]), sf);
         G->k[i] = narrow(f32v(kappa[i]), sf);
@@ -445,7 +446,8 @@ int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
     set_threads(nthreads);
     ac2d G, GE;   /* the step's coefficients; the energy's (fp32 values) */
     ac2d_setup(&G, nx, ny, order, dx, dt, rho, kappa, stencil);
-    ac2d_setup(&GE, nx, ny, order, dx, dt, rho, kappa, FMT_F32);
+    if (energy_every > 0)
+        ac2d_setup(&GE, nx, ny, order, dx, dt, rho, kappa, FMT_F32);
     arith A = {stencil, storage, comp};
     long m = 0;
     if (energy_every > 0)
@@ -465,7 +467,8 @@ int orc_acoustic2d(long nx, long ny, int order, double dx, double dt,
             energy[m++] = ac2d_energy(&GE, dx, vx, vy, p);
     }
     ac2d_free(&G);
-    ac2d_free(&GE);
+    if (energy_every > 0)
+        ac2d_free(&GE);
     return 0;
 }
 
