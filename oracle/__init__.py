@@ -26,7 +26,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FORMATS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
-COMPS = {"none": 0, "fast2sum": 1, "twosum": 2}
+COMPS = {"none": 0, "fast2sum": 1, "twosum": 2, "twosum8": 3}
 ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
 ACOUSTIC_FIELDS = ("vx", "vy", "p")
 
@@ -69,6 +69,8 @@ def lib():
         L.orc_twosum.argtypes = [D, D, I, P, P]
         L.orc_eft_check.restype = Lg
         L.orc_eft_check.argtypes = [I, I, P, Lg, P, Lg, I]
+        L.orc_quantize_comp.restype = D
+        L.orc_quantize_comp.argtypes = [D, D, I]
         L.orc_max_threads.restype = I
         L.orc_max_threads.argtypes = []
         L.orc_acoustic2d.restype = I
@@ -240,3 +242,9 @@ def elastic3d_energy(nx, ny, nz, dx, dt, rho, lam, mu, fields) -> float:
     return float(lib().orc_elastic3d_energy(
         nx, ny, nz, dx, dt, _ptr(rho), _ptr(lam), _ptr(mu),
         _ptr_array([f[k] for k in ELASTIC_FIELDS])))
+
+
+def quantize_comp(t: float, s: float, fmt: str) -> float:
+    """The compensation term t of the sum s as an 8-bit word holds it:
+    round(t / ulp(s) * 2^7) * ulp(s) / 2^7 (see orc_quantize_comp)."""
+    return float(lib().orc_quantize_comp(float(t), float(s), FORMATS[fmt]))

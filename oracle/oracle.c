@@ -56,7 +56,7 @@
 #endif
 
 enum { FMT_F64 = 0, FMT_F32 = 1, FMT_F16 = 2, FMT_BF16 = 3 };
-enum { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2 };
+enum { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2, COMP_TWOSUM8 = 3 };
 
 /* ------------------------------------------------------------------------ */
 /* Rounding to a binary floating-point format (Sec. 2, Table 1).            */
@@ -129,6 +129,41 @@ void orc_twosum(double a, double b, int fmt, double *s, double *t)
     *s = ss;
 }
 
+/* Spacing of the values of format fmt in the binade of s (for zero and
+ * subnormal s, the subnormal spacing). */
+static double ulp_of(double s, int fmt)
+{
+    int prec, emin;
+    switch (fmt) {
+    case FMT_F16: prec = 11; emin = -14; break;
+    case FMT_BF16: prec = 8; emin = -126; break;
+    case FMT_F32: prec = 24; emin = -126; break;
+    default: prec = 53; emin = -1022; break;
+    }
+    int lead = emin;
+    if (s != 0.0 && isfinite(s)) {
+        int e;
+        frexp(fabs(s), &e);          /* |s| = m 2^e, m in [1/2, 1) */
+        if (e - 1 > emin)
+            lead = e - 1;
+    }
+    return ldexp(1.0, lead - prec + 1);
+}
+
+/* The compensation term of a sum s held in 8 bits (the compensated sum
+ * with a narrow compensation word): t, whose magnitude is at most half the
+ * spacing of s's binade, is stored as the integer q = round(t / ulp(s) *
+ * 2^7) (ties to even, |q| <= 64) and read back as q * ulp(s) / 2^7.
+ * Returns the value read back (0 when s or t is not finite). */
+double orc_quantize_comp(double t, double s, int fmt)
+{
+    if (!isfinite(s) || !isfinite(t))
+        return 0.0;
+    double u = ulp_of(s, fmt);
+    double q = nearbyint(ldexp(t / u, 7));
+    return ldexp(q * u, -7);
+}
+
 /* Exactness check used by the tests: counts pairs (a[i], b[j]) with
  * a + b != s + t.  Equality of two exact sums of doubles is decided by
  * comparing their canonical double-double forms (fp64 TwoSum yields the
@@ -194,7 +229,9 @@ static void update(const arith *A, double *v, double *c, double inc)
     else
         orc_twosum(*v, y, A->tf, &s, &t);
     *v = s;
-    *c = t;
+    /* 8-bit compensation word: keep the part of t that 7 bits below s's
+     * last place hold */
+    *c = A->comp == COMP_TWOSUM8 ? orc_quantize_comp(t, s, A->tf) : t;
 }
 
 /* Neumaier's compensated summation in fp64, used for the energy. */
