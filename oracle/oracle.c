@@ -153,14 +153,17 @@ static double ulp_of(double s, int fmt)
 /* The compensation term of a sum s held in 8 bits (the compensated sum
  * with a narrow compensation word): t, whose magnitude is at most half the
  * spacing of s's binade, is stored as the integer q = round(t / ulp(s) *
- * 2^7) (ties to even, |q| <= 64) and read back as q * ulp(s) / 2^7.
- * Returns the value read back (0 when s or t is not finite). */
+ * 2^7) (ties to even, |q| <= 64) and read back as q * ulp(s) / 2^7; a
+ * zero word reads back as +0.  Returns the value read back (0 when s or t
+ * is not finite). */
 double orc_quantize_comp(double t, double s, int fmt)
 {
     if (!isfinite(s) || !isfinite(t))
         return 0.0;
     double u = ulp_of(s, fmt);
     double q = nearbyint(ldexp(t / u, 7));
+    if (q == 0.0)
+        q = 0.0;                     /* the word is an integer: no -0 */
     return ldexp(q * u, -7);
 }
 

@@ -31,6 +31,8 @@ def test_hand_values():
     assert Q(2.0 ** -31, 2.0 ** -20, "f16") == 2.0 ** -31     # subnormal s
     assert Q(3 * 2.0 ** -14, 1.0, "bf16") == 3 * 2.0 ** -14   # ulp 2^-7, q = 3
     assert Q(3 * 2.0 ** -15, 1.0, "bf16") == 2.0 ** -13       # q = 3/2 -> 2
+    assert math.copysign(1.0, Q(-2.0 ** -20, 1.0, "f16")) == 1.0   # +0, never -0
+    assert math.copysign(1.0, Q(-0.0, 1.0, "f16")) == 1.0
     assert Q(float("nan"), 1.0, "f16") == 0.0
     assert Q(1.0, float("inf"), "f16") == 0.0
 
@@ -142,7 +144,7 @@ def _native_step8(nx, ny, order, dt, rho, kappa, f, nsteps):
         pb = s - pa
         t = (v - pa) + (y - pb)
         u = ulp(s)
-        q = np.rint(t.astype(np.float64) / u * 128.0)    # ties to even
+        q = np.rint(t.astype(np.float64) / u * 128.0) + 0.0   # ties to even, no -0
         return s, (q * u / 128.0)
 
     st = {key: f[key].astype(h) for key in ("vx", "vy", "p")}
