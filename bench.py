@@ -36,13 +36,17 @@ ENERGY_EVERY = 1000
 # field (vx, vy, p) and, with compensation, every compensation term read and
 # written once, the two fp32 material arrays (b, kappa) read once.
 def bytes_per_cell(storage: str, comp: str) -> int:
+    """Algorithmic bytes per cell and step of the 2D step: three fields read
+    and written, their compensation terms (a storage-format value, or one
+    byte with 8-bit words) read and written, two fp32 material arrays read."""
     e = 4 if storage == "f32" else 2
     fields = 3 * e * 2
-    comps = 3 * e * 2 if comp != "none" else 0
+    comps = {"none": 0, "twosum8": 3 * 1 * 2}.get(comp, 3 * e * 2)
     return fields + comps + 2 * 4
 
 
-VARIANTS = [("f16", "twosum"), ("f32", "none"), ("f16", "none"), ("bf16", "none")]
+VARIANTS = [("f16", "twosum"), ("f32", "none"), ("f16", "none"), ("bf16", "none"),
+            ("f16", "twosum8")]
 
 
 def kernel_source_digest() -> str:
@@ -252,6 +256,7 @@ PAPER_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
 PAPER_VARIANTS = [("f32", "none", "f32"), ("f16", "none", "f32"),
                   ("f16", "fast2sum", "f32"), ("f16", "twosum", "f32"),
                   ("bf16", "none", "f32"), ("bf16", "twosum", "f32"),
+                  ("f16", "twosum8", "f32"),
                   # App. B: stencil promoted to fp64, update in fp16; and the
                   # all-fp16 step of Alg. 1 taken literally
                   ("f16", "none", "f64"), ("f16", "fast2sum", "f64"),

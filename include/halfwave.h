@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define HW_ABI_VERSION 4u
+#define HW_ABI_VERSION 5u
 
 typedef enum hw_status {
     HW_OK = 0,
@@ -72,7 +72,14 @@ typedef enum hw_status {
 
 enum hw_physics { HW_ACOUSTIC2D = 0, HW_ELASTIC3D = 1 };
 enum hw_storage { HW_F32 = 0, HW_F16 = 1, HW_BF16 = 2 };
-enum hw_comp { HW_COMP_NONE = 0, HW_COMP_FAST2SUM = 1, HW_COMP_TWOSUM = 2 };
+/* HW_COMP_TWOSUM8: the 6-operation sum with the compensation term held in
+ * an 8-bit word instead of a value of the storage format: the TwoSum error t
+ * of the new value s (|t| <= ulp(s)/2, ulp the spacing of s's binade) is
+ * kept as q = round(t / ulp(s) * 2^7), ties to even, and read back as
+ * q * ulp(s) / 2^7 -- 3 bytes of state per field and cell instead of 4.
+ * Acoustic plans with fp16 or bf16 storage only. */
+enum hw_comp { HW_COMP_NONE = 0, HW_COMP_FAST2SUM = 1, HW_COMP_TWOSUM = 2,
+               HW_COMP_TWOSUM8 = 3 };
 /* Precision of the stencil arithmetic (spatial differences, staggered
  * material, scaling by the material); the solution update is always in the
  * storage format.  HW_STENCIL_F32, the default, computes in fp32 from the

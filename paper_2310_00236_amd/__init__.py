@@ -23,14 +23,14 @@ LIB_PATH = os.path.join(_HERE, "libhalfwave.so")
 
 ACOUSTIC2D, ELASTIC3D = 0, 1
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
-COMP = {"none": 0, "fast2sum": 1, "twosum": 2}
+COMP = {"none": 0, "fast2sum": 1, "twosum": 2, "twosum8": 3}
 STENCIL = {"f32": 0, "storage": 1, "f64": 2}
 ACOUSTIC_FIELDS = ("vx", "vy", "p")
 ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
 STATUS = {0: "HW_OK", 1: "HW_E_INVAL", 2: "HW_E_UNSTABLE", 3: "HW_E_RANGE",
           4: "HW_E_NOMEM", 5: "HW_E_DEVICE", 6: "HW_E_NONFINITE",
           7: "HW_E_STATE"}
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class HalfwaveError(RuntimeError):

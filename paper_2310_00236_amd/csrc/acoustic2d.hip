@@ -144,6 +144,8 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
             else                                                                  \
                 hipLaunchKernelGGL((ac2d_step_kernel<S, COMP, ORDER, V, T>),      \
                                    grid, block, 0, s, a);                         \
+        } else if constexpr (COMP == COMP_TWOSUM8) {                              \
+            return hipErrorInvalidValue;   /* 8-bit words: tile kernels only */   \
         } else {                                                                  \
             if (one)                                                              \
                 hipLaunchKernelGGL((ac2d_march1_kernel<S, COMP, ORDER, V, T>),    \
@@ -183,6 +185,10 @@ static hipError_t step_comp(const Ac2dBatch &a, const Ac2dDesc *one, int comp,
         return step_order<S, COMP_FAST2SUM>(a, one, order, tile, forced, stencil, s);
     case COMP_TWOSUM:
         return step_order<S, COMP_TWOSUM>(a, one, order, tile, forced, stencil, s);
+    case COMP_TWOSUM8:
+        if constexpr (S::id != F32::id)
+            return step_order<S, COMP_TWOSUM8>(a, one, order, tile, forced, stencil, s);
+        break;
     }
     return hipErrorInvalidValue;
 }

@@ -161,6 +161,26 @@ __device__ __forceinline__ void update_one(typename Word<S, COMP>::type &w, floa
     w = WD::make(v, c);
 }
 
+// Updates of V cells whose compensation terms are 8-bit words q (held next
+// to the values, see update_store8).
+template <class S, int V>
+__device__ __forceinline__ void update_cells8(Cells<typename S::store_t, V> &c,
+                                              int8_t (&q)[V], const float (&inc)[V])
+{
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+        update_store8<S>(c.w[i], q[i], inc[i]);
+}
+
+template <class S, int V>
+__device__ __forceinline__ void update_cells8(Cells<typename S::store_t, V> &c,
+                                              int8_t (&q)[V], const double (&inc)[V])
+{
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+        update_store8_d<S>(c.w[i], q[i], inc[i]);
+}
+
 // Arithmetic of the stencil (the spatial differences, the staggered
 // material and the scaling; the solution update is always in the storage
 // format).  SP 0: fp32, the library's default.  SP 1: every operation in
@@ -260,7 +280,11 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                                           int y0, bool yin, float *ps, float *bs,
                                           float *vxs, float *vys)
 {
-    using WD = Word<S, COMP>;
+    // With 8-bit compensation words the value arrays hold values only (the
+    // words of a plain state) and the compensation bytes sit comp_off bytes
+    // after each value array.
+    constexpr bool C8 = COMP == COMP_TWOSUM8;
+    using WD = Word<S, C8 ? COMP_NONE : COMP>;
     using W = typename WD::type;
     using CV = Cells<W, V>;
     constexpr int TX = 64 * V;
@@ -289,6 +313,14 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     W HW_GLOBAL *__restrict__ p_out = gmem((W *)d.p[par ^ 1]);
     W HW_GLOBAL *__restrict__ vx_out = gmem((W *)d.vx[par ^ 1]);
     W HW_GLOBAL *__restrict__ vy_out = gmem((W *)d.vy[par ^ 1]);
+    using QP = const uint8_t HW_GLOBAL *;
+    using QO = uint8_t HW_GLOBAL *;
+    QP qp_in = gmem((const uint8_t *)d.p[par] + d.comp_off);
+    QP qx_in = gmem((const uint8_t *)d.vx[par] + d.comp_off);
+    QP qy_in = gmem((const uint8_t *)d.vy[par] + d.comp_off);
+    QO qp_out = gmem((uint8_t *)d.p[par ^ 1] + d.comp_off);
+    QO qx_out = gmem((uint8_t *)d.vx[par ^ 1] + d.comp_off);
+    QO qy_out = gmem((uint8_t *)d.vy[par ^ 1] + d.comp_off);
     const int xl = V * ln;                    // first tile column of the lane
     // point source and receivers: compiled in only for plans that have them
     const Forcing fc = FRC ? forcing(d) : Forcing{false, 0.0f, 0, 0, 0, 0};
@@ -313,6 +345,24 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
         } else {
             return ldw(base, row);
         }
+    };
+    // 8-bit compensation words of the lane's V cells of one row
+    auto ldq = [&](QP base, int row, int8_t (&out)[V]) {
+#pragma unroll
+        for (int c = 0; c < V; ++c)
+            out[c] = (int8_t)base[row + (WX ? gcol(xl + c) : x0 + xl + c)];
+    };
+    auto stq = [&](QO base, int row, const int8_t (&q)[V]) {
+#pragma unroll
+        for (int c = 0; c < V; ++c)
+            if (!WX || x0 + xl + c < nx)
+                __builtin_nontemporal_store((uint8_t)q[c], base + row + x0 + xl + c);
+    };
+    auto upd = [&](CV &cells, int8_t (&q)[V], const auto &inc) {
+        if constexpr (C8)
+            update_cells8<S, V>(cells, q, inc);
+        else
+            update_cells<S, COMP, V>(cells, inc);
     };
     // Halo columns: the cells of a region left and right of the tile, all
     // rows together, enumerated e = 0 .. NH-1 and handled one per thread,
@@ -345,6 +395,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     W vxh;
     CV vyw[KY];
     float km[KC][V];
+    int8_t qx[KC][V], qy[KY][V], qpp[KC][V], qxh = 0;   // 8-bit words
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         const int ly = -OP + wv + 4 * k;
@@ -372,14 +423,21 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     }
     if (tid < NHB)
         bh = b[grow(hb.ly) * pitch + gcol(hb.lx)];
-    if (tid < NHX && y0 + hx.ly < ny)
+    if (tid < NHX && y0 + hx.ly < ny) {
         vxh = vx_in[(y0 + hx.ly) * pitch + gcol(hx.lx)];
+        if constexpr (C8)
+            qxh = (int8_t)qx_in[(y0 + hx.ly) * pitch + gcol(hx.lx)];
+    }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
         const int ly = wv + 4 * k;
         if (y0 + ly < ny) {
             const int row = (y0 + ly) * pitch;
             vxw[k] = ldw_nt(vx_in, row);
+            if constexpr (C8) {
+                ldq(qx_in, row, qx[k]);
+                ldq(qp_in, row, qpp[k]);
+            }
             if constexpr (!WX) {
                 const float HW_GLOBAL *q = kap + row + x0 + xl;
 #pragma unroll
@@ -395,8 +453,11 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
         const int ly = -OB + wv + 4 * k;
-        if (ly >= -R && ly < TY + R - 1)
+        if (ly >= -R && ly < TY + R - 1) {
             vyw[k] = ldw(vy_in, grow(ly) * pitch);
+            if constexpr (C8)
+                ldq(qy_in, grow(ly) * pitch, qy[k]);
+        }
     }
 
     // ---- 2. old pressure and buoyancy to LDS
@@ -452,7 +513,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
 #pragma unroll
             for (int i = 0; i < V; ++i)
                 inc[i] = vx_inc(ly, xl + i);
-            update_cells<S, COMP, V>(vxw[k], inc);
+            upd(vxw[k], qx[k], inc);
             float *r = vxs + ly * VXW + R;
 #pragma unroll
             for (int i = 0; i < V; ++i)
@@ -472,10 +533,17 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                     if (x0 + xl + i < nx)
                         __builtin_nontemporal_store(vxw[k].w[i], o + i);
             }
+            if constexpr (C8)
+                stq(qx_out, (y0 + ly) * pitch, qx[k]);
         }
     }
     if (tid < NHX && y0 + hx.ly < ny) {
-        update_one<S, COMP>(vxh, vx_inc(hx.ly, hx.lx));
+        if constexpr (C8 && SP == 2)
+            update_store8_d<S>(vxh, qxh, vx_inc(hx.ly, hx.lx));
+        else if constexpr (C8)
+            update_store8<S>(vxh, qxh, vx_inc(hx.ly, hx.lx));
+        else
+            update_one<S, COMP>(vxh, vx_inc(hx.ly, hx.lx));
         vxs[hx.ly * VXW + R + hx.lx] = S::load(WD::v(vxh));
     }
 
@@ -500,7 +568,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                 const AT by = A::r(AT(0.5f) * A::r(A::m(bb[0]) + A::m(bb[BW])));
                 inc[i] = A::r(by * g);
             }
-            update_cells<S, COMP, V>(vyw[k], inc);
+            upd(vyw[k], qy[k], inc);
             float *r = vys + (ly + R) * TX;
 #pragma unroll
             for (int i = 0; i < V; ++i)
@@ -521,6 +589,8 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                         if (x0 + xl + i < nx)
                             __builtin_nontemporal_store(vyw[k].w[i], o + i);
                 }
+                if constexpr (C8)
+                    stq(qy_out, (y0 + ly) * pitch, qy[k]);
             }
         }
     }
@@ -556,7 +626,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                 inc[i] = A::r(A::m(km[k][i]) * dv);
             }
             CV &pc = pw[k + OP / 4];          // row ly's pressure words
-            update_cells<S, COMP, V>(pc, inc);
+            upd(pc, qpp[k], inc);
             if (fc.rn > 0) {
 #pragma unroll
                 for (int i = 0; i < V; ++i)
@@ -572,6 +642,8 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                     if (x0 + xl + i < nx)
                         __builtin_nontemporal_store(pc.w[i], o + i);
             }
+            if constexpr (C8)
+                stq(qp_out, (y0 + ly) * pitch, qpp[k]);
         }
     }
 }

@@ -59,6 +59,10 @@ static hipError_t variant_comp(const Ac2dBatch &a, const Ac2dDesc *one, int comp
     case COMP_NONE: return variant_order<S, COMP_NONE>(a, one, order, stencil, s);
     case COMP_FAST2SUM: return variant_order<S, COMP_FAST2SUM>(a, one, order, stencil, s);
     case COMP_TWOSUM: return variant_order<S, COMP_TWOSUM>(a, one, order, stencil, s);
+    case COMP_TWOSUM8:
+        if constexpr (S::id != F32::id)
+            return variant_order<S, COMP_TWOSUM8>(a, one, order, stencil, s);
+        break;
     }
     return hipErrorInvalidValue;
 }

@@ -36,6 +36,21 @@ __global__ __launch_bounds__(kThreads) void from_storage_kernel(
     }
 }
 
+template <class S>
+__global__ __launch_bounds__(kThreads) void comp8_kernel(
+    const typename S::store_t *__restrict__ v, const int8_t *__restrict__ q,
+    double *__restrict__ dst, int64_t nx, int64_t rows, int64_t pitch,
+    double scale)
+{
+    const int64_t n = nx * rows;
+    for (int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kThreads) {
+        const int64_t r = t / nx, i = t % nx;
+        const int64_t e = r * pitch + i;
+        dst[t] = (double)comp8_decode<S>(q[e], v[e]) * scale;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void fill_zero_kernel(uint32_t *dst,
                                                              int64_t n)
 {
@@ -112,6 +127,27 @@ hipError_t launch_from_storage(const void *src, double *dst, int storage,
     case HW_BF16:
         hipLaunchKernelGGL(from_storage_kernel<BF16>, g, b, 0, s,
                            (const uint16_t *)src, dst, nx, rows, pitch, stride, offset, scale);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_comp8_to_double(const void *values, size_t comp_off, double *dst,
+                                  int storage, int64_t nx, int64_t rows,
+                                  int64_t pitch, double scale, hipStream_t s)
+{
+    const dim3 g = grid_for(nx * rows), b(kThreads);
+    const int8_t *q = (const int8_t *)((const char *)values + comp_off);
+    switch (storage) {
+    case HW_F16:
+        hipLaunchKernelGGL(comp8_kernel<F16>, g, b, 0, s, (const _Float16 *)values, q,
+                           dst, nx, rows, pitch, scale);
+        break;
+    case HW_BF16:
+        hipLaunchKernelGGL(comp8_kernel<BF16>, g, b, 0, s, (const uint16_t *)values, q,
+                           dst, nx, rows, pitch, scale);
         break;
     default:
         return hipErrorInvalidValue;

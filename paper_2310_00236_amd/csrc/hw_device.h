@@ -17,7 +17,7 @@
 
 namespace hw {
 
-enum Comp { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2 };
+enum Comp { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2, COMP_TWOSUM8 = 3 };
 
 // ---------------------------------------------------------------- formats
 
@@ -201,22 +201,19 @@ __device__ __forceinline__ uint16_t from_double<BF16>(double x)
     return BF16::store((float)round_double(x, 8, -126, 0x1.fep127));
 }
 
-// The updates with an fp64 increment (the stencil evaluated in fp64): the
-// increment, or increment plus compensation, is rounded once to the storage
-// format; the sum that follows is the same as above.
-template <class S, int COMP>
-__device__ __forceinline__ void update_store_d(typename S::store_t &v,
-                                               typename S::store_t &c, double inc)
+// v <- v (+) y and, unless COMP_NONE, c <- the error (Fast2Sum or TwoSum),
+// all in format S; y is already a value of the format.
+template <class S, int COMP = COMP_TWOSUM>
+__device__ __forceinline__ void update_sum_store(typename S::store_t &v,
+                                                 typename S::store_t &c,
+                                                 typename S::store_t y)
 {
-    using T = typename S::store_t;
-    const T y = COMP == COMP_NONE ? from_double<S>(inc)
-                                  : from_double<S>(inc + (double)S::load(c));
     if constexpr (S::id == F16::id) {
         const _Float16 s = v + y;
         if constexpr (COMP == COMP_FAST2SUM) {
             const _Float16 z = s - v;
             c = y - z;
-        } else if constexpr (COMP == COMP_TWOSUM) {
+        } else if constexpr (COMP != COMP_NONE) {
             const _Float16 pa = s - y;
             const _Float16 pb = s - pa;
             const _Float16 da = v - pa;
@@ -230,7 +227,7 @@ __device__ __forceinline__ void update_store_d(typename S::store_t &v,
         if constexpr (COMP == COMP_FAST2SUM) {
             const float z = S::rn(s - vf);
             c = S::store(S::rn(yf - z));
-        } else if constexpr (COMP == COMP_TWOSUM) {
+        } else if constexpr (COMP != COMP_NONE) {
             const float pa = S::rn(s - yf);
             const float pb = S::rn(s - pa);
             const float da = S::rn(vf - pa);
@@ -239,6 +236,127 @@ __device__ __forceinline__ void update_store_d(typename S::store_t &v,
         }
         v = S::store(s);
     }
+}
+
+// The updates with an fp64 increment (the stencil evaluated in fp64): the
+// increment, or increment plus compensation, is rounded once to the storage
+// format; the sum that follows is the same as above.
+template <class S, int COMP>
+__device__ __forceinline__ void update_store_d(typename S::store_t &v,
+                                               typename S::store_t &c, double inc)
+{
+    using T = typename S::store_t;
+    const T y = COMP == COMP_NONE ? from_double<S>(inc)
+                                  : from_double<S>(inc + (double)S::load(c));
+    update_sum_store<S, COMP>(v, c, y);
+}
+
+// ------------------------------------------ 8-bit compensation word
+//
+// With COMP_TWOSUM8 the TwoSum error t of a sum s (|t| <= ulp(s)/2, ulp the
+// spacing of s's binade, the subnormal spacing for zero and subnormal s) is
+// kept as the integer q = round(t / ulp(s) * 2^7), ties to even, |q| <= 64,
+// one byte per cell next to the value array, and read back as
+// q * ulp(s) / 2^7.  Both scalings are exact powers of two.
+
+// Biased exponent field of s, and whether s is finite.
+__device__ __forceinline__ uint32_t exp_field(_Float16 s)
+{
+    return (__builtin_bit_cast(uint16_t, s) >> 10) & 0x1fu;
+}
+__device__ __forceinline__ uint32_t exp_field_bf16(uint16_t s)
+{
+    return (s >> 7) & 0xffu;
+}
+
+// One step of q is ulp(s) / 2^7, with ulp(s) = 2^(max(E,1) - 25) for fp16
+// (E the exponent field; E = 0 gives the subnormal spacing 2^-24) and
+// 2^(max(E,1) - 134) for bf16.  For fp16 the power of two and its inverse
+// are normal fp32 numbers, built from their exponent fields; for bf16 they
+// can leave the fp32 range, so the scaling goes through ldexpf.  Either
+// way the scaling is exact.
+template <class S>
+__device__ __forceinline__ float comp8_decode(int8_t q, typename S::store_t s)
+{
+    if constexpr (S::id == F16::id) {
+        const uint32_t e = max(exp_field(s), 1u);
+        return (float)q * __uint_as_float((e + 95u) << 23);   // q 2^(e - 32)
+    } else {
+        const int e = (int)max(exp_field_bf16(s), 1u);
+        return ldexpf((float)q, e - 141);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ float comp8_scale_up(float t, typename S::store_t s)
+{
+    if constexpr (S::id == F16::id) {
+        const uint32_t e = max(exp_field(s), 1u);
+        return t * __uint_as_float((159u - e) << 23);          // t 2^(32 - e)
+    } else {
+        const int e = (int)max(exp_field_bf16(s), 1u);
+        return ldexpf(t, 141 - e);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ bool comp8_finite(typename S::store_t s)
+{
+    if constexpr (S::id == F16::id)
+        return exp_field(s) != 0x1fu;
+    else
+        return exp_field_bf16(s) != 0xffu;
+}
+
+// q = round(t / ulp(s) * 2^7), ties to even; 0 when s or t is not finite
+// (an operation of the sum overflowed).  |t| <= ulp(s)/2 keeps |q| <= 64.
+template <class S>
+__device__ __forceinline__ int8_t comp8_encode(float t, typename S::store_t s)
+{
+    if (!comp8_finite<S>(s) || !isfinite(t))
+        return 0;
+    return (int8_t)(int)rintf(comp8_scale_up<S>(t, s));
+}
+
+// The compensated update with the 8-bit word: y = RN(inc + t_old), the
+// 6-operation sum of v and y in format S, the new error re-quantised.
+template <class S>
+__device__ __forceinline__ void update_store8(typename S::store_t &v, int8_t &q, float inc)
+{
+    const float told = comp8_decode<S>(q, v);
+    if constexpr (S::id == F16::id) {
+        const _Float16 y = (_Float16)opaque(inc + told);
+        const _Float16 s = v + y;
+        const _Float16 pa = s - y;
+        const _Float16 pb = s - pa;
+        const _Float16 da = v - pa;
+        const _Float16 db = y - pb;
+        const _Float16 t = da + db;
+        q = comp8_encode<S>((float)t, s);
+        v = s;
+    } else {
+        const float vf = S::load(v);
+        const float y = S::rn(inc + told);
+        const float s = S::rn(vf + y);
+        const float pa = S::rn(s - y);
+        const float pb = S::rn(s - pa);
+        const float da = S::rn(vf - pa);
+        const float db = S::rn(y - pb);
+        const float t = S::rn(da + db);
+        v = S::store(s);
+        q = comp8_encode<S>(t, v);
+    }
+}
+
+// The same with an fp64 increment (stencil in fp64).
+template <class S>
+__device__ __forceinline__ void update_store8_d(typename S::store_t &v, int8_t &q, double inc)
+{
+    using T = typename S::store_t;
+    const T y = from_double<S>(inc + (double)comp8_decode<S>(q, v));
+    T c = T(0);
+    update_sum_store<S>(v, c, y);
+    q = comp8_encode<S>(S::load(c), v);
 }
 
 // Memory word of one field at one cell: the value alone, or the value and

@@ -24,6 +24,9 @@ struct Ac2dDesc {
     const float *b;               // 1/rho at p points
     const float *k;               // kappa at p points
     void *vx[2], *vy[2], *p[2];   // field sets (storage words)
+    int64_t comp_off;             // 8-bit compensation words: their bytes
+                                  // start this many bytes after each value
+                                  // array (0 when unused)
     // point source and receivers (src_n == 0 and rec_n == 0 when unused)
     const int64_t *step;          // device count of steps since the upload
     const float *src;             // per-step source samples (fp32)
@@ -136,6 +139,11 @@ hipError_t launch_from_storage(const void *src, double *dst, int storage,
                                int stride, int offset, double scale,
                                hipStream_t s);
 hipError_t launch_fill_zero(void *dst, size_t bytes, hipStream_t s);
+// The compensation terms of a field held as 8-bit words (comp_off bytes
+// after its value array) as fp64: q * ulp(value) / 2^7, times scale.
+hipError_t launch_comp8_to_double(const void *values, size_t comp_off, double *dst,
+                                  int storage, int64_t nx, int64_t rows,
+                                  int64_t pitch, double scale, hipStream_t s);
 hipError_t launch_material(const double *src, float *dst, int reciprocal,
                            int64_t nx, int64_t rows, int64_t pitch,
                            hipStream_t s);

@@ -70,6 +70,8 @@ struct Layout {
     int nf = 0, nm = 0, sets = 1;
     int64_t pitch = 0, slab = 0, rows = 0, cells = 0;
     int words = 1;                 // storage values per cell and field
+    bool c8 = false;               // 8-bit compensation words
+    size_t comp_off = 0;           // their offset after each value array
     size_t field_bytes = 0, mat_bytes = 0;
     size_t off_fld[2][9] = {};
     size_t off_mat[3] = {}, off_staging = 0, off_partial = 0, off_trace = 0;
@@ -89,8 +91,12 @@ hw_status validate(const hw_problem *pb)
         return fail(HW_E_INVAL, "unsupported order for this physics");
     if (pb->storage < HW_F32 || pb->storage > HW_BF16)
         return fail(HW_E_INVAL, "unknown storage format");
-    if (pb->comp < HW_COMP_NONE || pb->comp > HW_COMP_TWOSUM)
+    if (pb->comp < HW_COMP_NONE || pb->comp > HW_COMP_TWOSUM8)
         return fail(HW_E_INVAL, "unknown compensation mode");
+    if (pb->comp == HW_COMP_TWOSUM8 &&
+        (pb->physics != HW_ACOUSTIC2D || pb->storage == HW_F32))
+        return fail(HW_E_INVAL, "8-bit compensation words are for acoustic "
+                                "fp16 / bf16 plans");
     if (pb->scale_log2 < -60 || pb->scale_log2 > 60)
         return fail(HW_E_INVAL, "scale_log2 out of [-60, 60]");
     if (pb->nx < 1 || pb->ny < 1 || pb->nz < 1)
@@ -144,8 +150,12 @@ Layout make_layout(const hw_problem *pb)
     L.rows = pb->ny * pb->nz;
     L.cells = pb->nx * pb->ny * pb->nz;
     // with compensation each cell holds (value, compensation) side by side
-    L.words = pb->comp != HW_COMP_NONE ? 2 : 1;
-    L.field_bytes = align_up((size_t)(L.slab * pb->nz) * esize(pb->storage) * L.words,
+    // 8-bit compensation words: a byte array after each value array
+    L.c8 = pb->comp == HW_COMP_TWOSUM8;
+    L.words = pb->comp != HW_COMP_NONE && !L.c8 ? 2 : 1;
+    L.comp_off = L.c8 ? (size_t)(L.slab * pb->nz) * esize(pb->storage) : 0;
+    L.field_bytes = align_up((size_t)(L.slab * pb->nz) * esize(pb->storage) * L.words +
+                                 (L.c8 ? (size_t)(L.slab * pb->nz) : 0),
                              kAlign);
     L.mat_bytes = align_up((size_t)(L.slab * pb->nz) * 4, kAlign);
     size_t off = 0;
@@ -262,7 +272,11 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             for (int i = 0; i < m; ++i)
                 forced = forced || plans[base + i]->counts();
             const int stencil = p0->pb.stencil;
-            const int t = forced || stencil != HW_STENCIL_F32 ? 0 : tile;
+            // variants and 8-bit compensation words run on tile kernels
+            const bool tile_only = forced || stencil != HW_STENCIL_F32 ||
+                                   (p0->pb.comp == HW_COMP_TWOSUM8 &&
+                                    kTiles2D[tile].kind != 0);
+            const int t = tile_only ? 0 : tile;
             int64_t total = 0;
             for (int i = 0; i < m; ++i) {
                 hw_plan *p = plans[base + i];
@@ -714,6 +728,7 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
             d.vy[s] = p->fld[s][1];
             d.p[s] = p->fld[s][2];
         }
+        d.comp_off = (int64_t)L.comp_off;
         p->counter = (int64_t *)(p->arena + L.off_flags + 8);
         d.step = p->counter;
         d.src = (const float *)(p->arena + L.off_src);
@@ -861,9 +876,14 @@ hw_status hw_get_fields(hw_plan *p, double *const *fields, double *const *comps,
                 std::memset(dst[f], 0, bytes);
                 continue;
             }
-            HW_HIP(launch_from_storage(p->fld[p->cur][f], p->staging, p->pb.storage,
-                                       p->pb.nx, p->L.rows, p->L.pitch, p->L.words,
-                                       pass, p->scale_down, s));
+            if (pass == 1 && p->L.c8)
+                HW_HIP(launch_comp8_to_double(p->fld[p->cur][f], p->L.comp_off,
+                                              p->staging, p->pb.storage, p->pb.nx,
+                                              p->L.rows, p->L.pitch, p->scale_down, s));
+            else
+                HW_HIP(launch_from_storage(p->fld[p->cur][f], p->staging, p->pb.storage,
+                                           p->pb.nx, p->L.rows, p->L.pitch, p->L.words,
+                                           pass, p->scale_down, s));
             HW_HIP(hipMemcpyAsync(dst[f], p->staging, bytes, hipMemcpyDeviceToHost, s));
         }
     }

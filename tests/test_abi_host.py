@@ -71,6 +71,8 @@ def _pb(**kw):
     dict(physics="elastic3d", nz=4, order=2, src_cap=8),
     dict(physics="elastic3d", nz=4, order=2, rec_cap=1, rec_steps=4),
     dict(physics="elastic3d", nz=4, order=2, stencil="f64"),
+    dict(comp="twosum8", storage="f32"),
+    dict(physics="elastic3d", nz=4, order=2, comp="twosum8"),
 ])
 def test_invalid_problems(kw):
     with pytest.raises(hw.HalfwaveError) as ei:
@@ -79,7 +81,7 @@ def test_invalid_problems(kw):
 
 
 def test_invalid_enums_and_abi():
-    for field, val in (("storage", 7), ("comp", 5), ("physics", 3),
+    for field, val in (("storage", 7), ("comp", 4), ("physics", 3),
                        ("abi_version", 99), ("stencil", 3), ("stencil", -1)):
         c = _pb().c()
         setattr(c, field, val)
@@ -89,9 +91,10 @@ def test_invalid_enums_and_abi():
 
 def test_footprint_grows_with_precision_and_compensation():
     f16 = hw.footprint(_pb(storage="f16", comp="none"))
+    f16c8 = hw.footprint(_pb(storage="f16", comp="twosum8"))
     f16c = hw.footprint(_pb(storage="f16", comp="twosum"))
     f32 = hw.footprint(_pb(storage="f32", comp="none"))
-    assert f16 < f16c and f16 < f32
+    assert f16 < f16c8 < f16c and f16 < f32
 
 
 def _plan(pb, arena_bytes=None):
