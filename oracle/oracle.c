@@ -55,6 +55,13 @@
 #include <omp.h>
 #endif
 
+/* Loops over fewer cells than this run on one thread: a parallel region
+ * costs more than the work, and many oracle processes side by side would
+ * otherwise contend for the cores at every step.  Every loop computes each
+ * cell (or row partial) on its own, so the thread count never changes a
+ * result. */
+#define PAR_MIN (1L << 15)
+
 enum { FMT_F64 = 0, FMT_F32 = 1, FMT_F16 = 2, FMT_BF16 = 3 };
 enum { COMP_NONE = 0, COMP_FAST2SUM = 1, COMP_TWOSUM = 2, COMP_TWOSUM8 = 3 };
 
@@ -301,7 +308,7 @@ static void ac2d_setup(ac2d *G, long nx, long ny, int order, double dx,
     long n = nx * ny;
     G->b = malloc(sizeof(double) * n);
     G->k = malloc(sizeof(double) * n);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (n >= PAR_MIN)
     for (long i = 0; i < n; ++i) {
         G->b[i] = narrow(f32v(1.0 / rho[i]), sf);
         G->k[i] = narrow(f32v(kappa[i]), sf);
@@ -327,7 +334,7 @@ static void ac2d_step(const ac2d *G, const arith *A, double *vx, double *vy,
 #define S(x) orc_round((x), sf)
 
     /* vx at (i+1/2, j): dp/dx */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
     for (long j = 0; j < ny; ++j)
         for (long i = 0; i < nx; ++i) {
             double a0 = S(p[IX(j, i + 1)] - p[IX(j, i)]);
@@ -345,7 +352,7 @@ static void ac2d_step(const ac2d *G, const arith *A, double *vx, double *vy,
         }
 
     /* vy at (i, j+1/2): dp/dy */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
     for (long j = 0; j < ny; ++j)
         for (long i = 0; i < nx; ++i) {
             double a0 = S(p[IX(j + 1, i)] - p[IX(j, i)]);
@@ -363,7 +370,7 @@ static void ac2d_step(const ac2d *G, const arith *A, double *vx, double *vy,
         }
 
     /* p at (i, j): dvx/dx + dvy/dy */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
     for (long j = 0; j < ny; ++j)
         for (long i = 0; i < nx; ++i) {
             double ax0 = S(vx[IX(j, i)] - vx[IX(j, i - 1)]);
@@ -402,7 +409,7 @@ static double ac2d_energy(const ac2d *G, double dx, const double *vx,
     const long nx = G->nx, ny = G->ny;
     const double w1 = G->w1, w2 = G->w2;
     double *rows = malloc(sizeof(double) * 2 * ny);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
     for (long j = 0; j < ny; ++j) {
         nsum acc = {0.0, 0.0};
         for (long i = 0; i < nx; ++i) {
@@ -586,7 +593,7 @@ static void el3d_step(const el3d *G, const arith *A, double *const *f,
 #define CP(a, q) ((a) ? &(a)[q] : NULL)
 
     /* velocities: rho dv/dt = div sigma */
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (nx * ny * nz >= PAR_MIN)
     for (long k = 0; k < nz; ++k)
         for (long j = 0; j < ny; ++j)
             for (long i = 0; i < nx; ++i) {
@@ -618,7 +625,7 @@ static void el3d_step(const el3d *G, const arith *A, double *const *f,
             }
 
     /* stresses: dsigma/dt = lambda tr(e) I + 2 mu e, e the strain rate */
-#pragma omp parallel for collapse(2) schedule(static)
+#pragma omp parallel for collapse(2) schedule(static) if (nx * ny * nz >= PAR_MIN)
     for (long k = 0; k < nz; ++k)
         for (long j = 0; j < ny; ++j)
             for (long i = 0; i < nx; ++i) {
@@ -677,7 +684,7 @@ static double el3d_energy(const el3d *G, double dx, double *const *f)
     const double *B = G->b, *L = G->lam, *M = G->mu;
     long nrows = ny * nz;
     double *rows = malloc(sizeof(double) * 2 * nrows);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nrows * nx >= PAR_MIN)
     for (long r = 0; r < nrows; ++r) {
         long k = r / ny, j = r % ny;
         nsum acc = {0.0, 0.0};
