@@ -788,8 +788,12 @@ hw_status hw_set_fields(hw_plan *p, const double *const *fields, void *stream)
         return st;
     hipStream_t s = S(stream);
     for (int f = 0; f < p->L.nf; ++f) {
-        // zero values and compensation terms, then write the values
+        // zero values and compensation terms, then write the values; the
+        // other field set is cleared too, since the kernels never write its
+        // padding and an exported state must not depend on the arena's past
         HW_HIP(launch_fill_zero(p->fld[0][f], p->L.field_bytes, s));
+        if (p->L.sets > 1)
+            HW_HIP(launch_fill_zero(p->fld[1][f], p->L.field_bytes, s));
         if (!fields[f])
             continue;
         HW_HIP(hipMemcpyAsync(p->staging, fields[f], (size_t)p->L.cells * 8,
@@ -959,9 +963,12 @@ hw_status hw_state_import(hw_plan *p, const void *blob, size_t bytes, void *stre
         return fail(HW_E_INVAL, "blob does not match this plan's problem");
     hipStream_t s = S(stream);
     const char *src = (const char *)blob + sizeof(h);
-    for (int f = 0; f < p->L.nf; ++f, src += p->L.field_bytes)
+    for (int f = 0; f < p->L.nf; ++f, src += p->L.field_bytes) {
         HW_HIP(hipMemcpyAsync(p->fld[0][f], src, p->L.field_bytes,
                               hipMemcpyHostToDevice, s));
+        if (p->L.sets > 1)         // padding of the other set (see hw_set_fields)
+            HW_HIP(launch_fill_zero(p->fld[1][f], p->L.field_bytes, s));
+    }
     HW_HIP(launch_fill_zero(p->flags, kAlign, s));
     if (p->counter)
         HW_HIP(launch_set_counter(p->counter, h.step, s));
