@@ -29,6 +29,7 @@ FORMATS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 COMPS = {"none": 0, "fast2sum": 1, "twosum": 2, "twosum8": 3}
 ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
 ACOUSTIC_FIELDS = ("vx", "vy", "p")
+ELASTIC2D_FIELDS = ("vx", "vy", "sxx", "syy", "sxy")
 
 # The compile line is part of the oracle's definition: no contraction of
 # a*b+c into fused multiply-adds, no fast-math value changes.
@@ -85,6 +86,11 @@ def lib():
                                     I, I, I, Lg, Lg, P, I]
         L.orc_elastic3d_energy.restype = D
         L.orc_elastic3d_energy.argtypes = [Lg, Lg, Lg, D, D, P, P, P, PP]
+        L.orc_elastic2d.restype = I
+        L.orc_elastic2d.argtypes = [Lg, Lg, D, D, P, P, P, PP, PP, I, I, I,
+                                    Lg, Lg, P, I, Lg, Lg, P, Lg, Lg, PL, PL, P]
+        L.orc_elastic2d_energy.restype = D
+        L.orc_elastic2d_energy.argtypes = [Lg, Lg, D, D, P, P, P, PP]
         _lib = L
     return _lib
 
@@ -242,6 +248,65 @@ def elastic3d_energy(nx, ny, nz, dx, dt, rho, lam, mu, fields) -> float:
     return float(lib().orc_elastic3d_energy(
         nx, ny, nz, dx, dt, _ptr(rho), _ptr(lam), _ptr(mu),
         _ptr_array([f[k] for k in ELASTIC_FIELDS])))
+
+
+def elastic2d(nx, ny, dx, dt, rho, lam, mu, fields, *, storage="f64",
+              stencil="f64", comp="none", comps=None, nsteps=0,
+              energy_every=0, nthreads=0, source=None, receivers=None):
+    """Advance the 2D velocity-stress system of Eq. (A1), App. A (periodic
+    in x, free surfaces on rows 0 and ny-1) by nsteps leapfrog steps.
+
+    fields: dict keyed by ELASTIC2D_FIELDS, [ny, nx] arrays (syy zero on
+    both surface rows, vy and sxy zero on row ny-1); material rho, lambda,
+    mu at cells.  source: (ix, iy, samples) -- step n of this call adds
+    samples[n] (rounded to the stencil format) to vy at (ix, iy + 1/2)
+    after the division by rho.  receivers: list of (ix, iy) cells; after
+    step n, trace[n, r] holds the five fields there.  Returns (fields,
+    comps, energy), plus the trace [nsteps, nrec, 5] when receivers are
+    given.
+    """
+    shape = (ny, nx)
+    rho, lam, mu = (_f64(a, shape) for a in (rho, lam, mu))
+    f = {k: _f64(fields[k], shape).copy() for k in ELASTIC2D_FIELDS}
+    if comp != "none":
+        c = {k: (_f64(comps[k], shape).copy() if comps is not None
+                 else np.zeros(shape)) for k in ELASTIC2D_FIELDS}
+        cptr = _ptr_array([c[k] for k in ELASTIC2D_FIELDS])
+    else:
+        c = {k: None for k in ELASTIC2D_FIELDS}
+        cptr = None
+    fptr = _ptr_array([f[k] for k in ELASTIC2D_FIELDS])
+    ne = nsteps // energy_every + 1 if energy_every > 0 else 0
+    energy = np.zeros(max(ne, 1))
+    sx, sy, samples = (0, 0, np.zeros(1)) if source is None else source
+    samples = np.ascontiguousarray(samples, dtype=np.float64)
+    nsrc = 0 if source is None else len(samples)
+    rec = [] if receivers is None else list(receivers)
+    PL = ctypes.POINTER(ctypes.c_long)
+    rx = np.ascontiguousarray([r[0] for r in rec] or [0], dtype=np.int64)
+    ry = np.ascontiguousarray([r[1] for r in rec] or [0], dtype=np.int64)
+    nf = len(ELASTIC2D_FIELDS)
+    trace = np.zeros((max(nsteps, 1), max(len(rec), 1), nf))
+    rc = lib().orc_elastic2d(nx, ny, dx, dt, _ptr(rho), _ptr(lam), _ptr(mu),
+                             fptr, cptr, FORMATS[storage], FORMATS[stencil],
+                             COMPS[comp], nsteps, energy_every, _ptr(energy),
+                             nthreads, int(sx), int(sy), _ptr(samples), nsrc,
+                             len(rec), rx.ctypes.data_as(PL),
+                             ry.ctypes.data_as(PL), _ptr(trace))
+    if rc != 0:
+        raise ValueError("oracle rejected the elastic2d arguments")
+    if receivers is not None:
+        return f, c, energy[:ne], trace[:nsteps, :len(rec)]
+    return f, c, energy[:ne]
+
+
+def elastic2d_energy(nx, ny, dx, dt, rho, lam, mu, fields) -> float:
+    shape = (ny, nx)
+    rho, lam, mu = (_f64(a, shape) for a in (rho, lam, mu))
+    f = {k: _f64(fields[k], shape) for k in ELASTIC2D_FIELDS}
+    return float(lib().orc_elastic2d_energy(
+        nx, ny, dx, dt, _ptr(rho), _ptr(lam), _ptr(mu),
+        _ptr_array([f[k] for k in ELASTIC2D_FIELDS])))
 
 
 def quantize_comp(t: float, s: float, fmt: str) -> float:

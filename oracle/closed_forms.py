@@ -136,3 +136,65 @@ def elastic_s_mode(nx, ny, nz, dx, dt, rho, lam, mu, m, n, axis_pair):
     f["v" + vel][...] = v.reshape(bshape)
     f[stress][...] = sig.reshape(bshape)
     return f
+
+
+def elastic2d_surface_modes(nx, ny, dt, rho, lam, mu, m, n, kind):
+    """Standing modes along y of the 2D elastic system of Eq. (A1) between
+    the two free surfaces (rows 0 and L = ny-1), uniform in x, homogeneous
+    medium, dx = 1, state (v^{n-1/2}, sigma^n).  k = m pi / L.
+
+    kind 'p' (compressional, vy/syy/sxx):
+        syy_j^n = A cos(w n dt) sin(k j)             (zero on both surfaces)
+        vy_{j+1/2}^{n+1/2} = V sin(w (n+1/2) dt) cos(k (j+1/2))
+        sxx_j^n = (lam / l2m) syy_j^n on interior rows, 0 on the surfaces
+      with s = sin(w dt / 2) = w_ * sqrt(b l2m) sin(k/2)  (w_ = fp32 dt/dx),
+      V = A b w_ sin(k/2) / s, and l2m = fp32(lam + 2 mu), b = fp32(1/rho).
+    kind 's' (shear, vx/sxy):
+        sxy_{j+1/2}^n = A cos(w n dt) sin(k (j+1/2))  (odd about each surface)
+        vx_j^{n+1/2}  = V sin(w (n+1/2) dt) cos(k j)
+      with s = w_ sqrt(b mu) sin(k/2), A = V s / (b w_ sin(k/2)).
+
+    Both follow from substituting the ansatz into the update equations: the
+    difference of sin(k j) across a half cell is 2 cos(k (j+1/2)) sin(k/2),
+    the difference of cos across a half cell is -2 sin(.) sin(k/2), and
+    the leapfrog difference of cos(w n dt) is -2 sin(w (n+1/2) dt) s.  For
+    the shear mode the image rule of the surfaces (sxy half a cell outside
+    equals minus sxy half a cell inside) holds for the ansatz because
+    sin(k (L + 1/2)) = -sin(k (L - 1/2)) when k L is a multiple of pi.
+    Returns a dict of the five fields, [ny, nx].
+    """
+    L = ny - 1
+    k = m * math.pi / L
+    w_ = f32(dt)                  # dx = 1
+    b = f32(1.0 / rho)
+    j = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    z = np.zeros((ny, nx))
+    out = {"vx": z.copy(), "vy": z.copy(), "sxx": z.copy(), "syy": z.copy(),
+           "sxy": z.copy()}
+    if kind == "p":
+        l2m = f32(lam + 2.0 * mu)
+        lm = f32(lam)
+        s = w_ * math.sqrt(b * l2m) * math.sin(k / 2)
+        om = 2.0 * math.asin(s)
+        A = 1.0
+        V = A * b * w_ * math.sin(k / 2) / s
+        syy = A * math.cos(om * n) * np.sin(k * j)
+        syy[0] = 0.0
+        syy[-1] = 0.0
+        # vy^{n+1/2} = V sin(w (n+1/2) dt) cos(k (j+1/2)); the state holds
+        # the value half a step back
+        vy = V * math.sin(om * (n - 0.5)) * np.cos(k * (j + 0.5))
+        vy[-1] = 0.0
+        sxx = (lm / l2m) * syy
+        out.update(vy=vy, syy=syy, sxx=sxx)
+    else:
+        mq = f32(mu)
+        s = w_ * math.sqrt(b * mq) * math.sin(k / 2)
+        om = 2.0 * math.asin(s)
+        V = 1.0
+        A = V * s / (b * w_ * math.sin(k / 2))
+        vx = V * math.sin(om * (n - 0.5)) * np.cos(k * j)
+        sxy = A * math.cos(om * n) * np.sin(k * (j + 0.5))
+        sxy[-1] = 0.0
+        out.update(vx=vx, sxy=sxy)
+    return out

@@ -20,6 +20,9 @@
  *     Fast2Sum) and the 6-operation form (Code 2, TwoSum).
  *   - The 3D velocity-stress elastic system, the 3D extension of Eq. (A1)
  *     of App. A, on the standard staggered (Virieux) layout.
+ *   - The 2D velocity-stress elastic system of Eq. (A1), App. A, periodic
+ *     in x and bounded in y by free surfaces, with the point source on the
+ *     vertical velocity (the s^{vy} term) and receivers.
  *   - The discrete energy of the staggered leapfrog scheme (Sec. 3 uses it
  *     as the diagnosis tool but defers its formula; the form used here is
  *     derived from the scheme and conserved exactly in exact arithmetic).
@@ -783,3 +786,282 @@ double orc_elastic3d_energy(long nx, long ny, long nz, double dx, double dt,
 }
 
 #undef IX3
+
+/* ------------------------------------------------------------------------ */
+/* 2D elastic (velocity-stress, Eq. A1 of App. A), 2nd order, periodic in x */
+/* and bounded in y by two free surfaces.                                   */
+/*                                                                          */
+/* Layout (arrays [ny][nx], x fastest):                                     */
+/*   sxx, syy, material  at (i,     j    ),  j = 0 .. ny-1                  */
+/*   vx                  at (i+1/2, j    ),  j = 0 .. ny-1                  */
+/*   vy                  at (i,     j+1/2),  j = 0 .. ny-2                  */
+/*   sxy                 at (i+1/2, j+1/2),  j = 0 .. ny-2                  */
+/* Field order everywhere: vx, vy, sxx, syy, sxy.  Row ny-1 of vy and sxy   */
+/* lies outside the body; it is held at zero and never updated.             */
+/*                                                                          */
+/* The surfaces are the normal-stress rows j = 0 and j = ny-1, where the    */
+/* traction vanishes: syy is held at zero, sxy is odd about the surface     */
+/* (the value half a cell outside is minus the value half a cell inside),   */
+/* and sxx, with the vertical strain rate eliminated through syy = 0,       */
+/* changes by the plate modulus 4 mu (lambda + mu) / (lambda + 2 mu) times  */
+/* the horizontal strain rate.  With half weights on the two surface rows   */
+/* the discrete divergence is minus the adjoint of the discrete gradient,   */
+/* so the leapfrog energy below is conserved exactly in exact arithmetic.   */
+/* ------------------------------------------------------------------------ */
+
+enum { EL2D_NF = 5 };
+
+typedef struct {
+    long nx, ny;
+    double w;
+    double *b;     /* fp32 1/rho at cells */
+    double *l2m;   /* fp32 lambda + 2 mu; the plate modulus on surface rows */
+    double *lam;   /* fp32 lambda; 0 on surface rows */
+    double *mxy;   /* fp32 mean of the four mu around each sxy point */
+} el2d;
+
+#define IX2(j, i) ((j) * G->nx + wrap((i), G->nx))
+
+static void el2d_setup(el2d *G, long nx, long ny, double dx, double dt,
+                       const double *rho, const double *lam, const double *mu)
+{
+    G->nx = nx;
+    G->ny = ny;
+    G->w = f32v(1.0 * (dt / dx));
+    long n = nx * ny;
+    G->b = malloc(sizeof(double) * n);
+    G->l2m = malloc(sizeof(double) * n);
+    G->lam = malloc(sizeof(double) * n);
+    G->mxy = malloc(sizeof(double) * n);
+    for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+            long q = j * nx + i;
+            int surface = j == 0 || j == ny - 1;
+            G->b[q] = f32v(1.0 / rho[q]);
+            if (surface) {
+                G->l2m[q] = f32v((4.0 * mu[q] * (lam[q] + mu[q])) /
+                                 (lam[q] + 2.0 * mu[q]));
+                G->lam[q] = 0.0;
+            } else {
+                G->l2m[q] = f32v(lam[q] + 2.0 * mu[q]);
+                G->lam[q] = f32v(lam[q]);
+            }
+            G->mxy[q] = j < ny - 1
+                ? f32v(0.25 * ((mu[q] + mu[IX2(j, i + 1)]) +
+                               (mu[IX2(j + 1, i)] + mu[IX2(j + 1, i + 1)])))
+                : 0.0;
+        }
+}
+
+static void el2d_free(el2d *G)
+{
+    free(G->b);
+    free(G->l2m);
+    free(G->lam);
+    free(G->mxy);
+}
+
+/* sxy just below and just above the vx point (i+1/2, j), the images across
+ * the surfaces included. */
+static double sxy_lo(const el2d *G, const double *sxy, long j, long i)
+{
+    return j == 0 ? -sxy[IX2(0, i)] : sxy[IX2(j - 1, i)];
+}
+
+static double sxy_hi(const el2d *G, const double *sxy, long j, long i)
+{
+    return j == G->ny - 1 ? -sxy[IX2(G->ny - 2, i)] : sxy[IX2(j, i)];
+}
+
+/* One step: velocities from the old stresses (and the v_y point source),
+ * then stresses from the new velocities; in place (the velocity loop reads
+ * only stresses, the stress loop only velocities and each cell's own
+ * stresses). */
+static void el2d_step(const el2d *G, const arith *A, double *const *f,
+                      double *const *c, long src_q, double src_val)
+{
+    const int sf = A->sf;
+    const long nx = G->nx, ny = G->ny;
+    const double w = G->w;
+    double *vx = f[0], *vy = f[1], *sxx = f[2], *syy = f[3], *sxy = f[4];
+    const double *B = G->b;
+#define S(x) orc_round((x), sf)
+#define CP(a, q) ((a) ? &(a)[q] : NULL)
+
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
+    for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+            long q = j * nx + i;
+            {   /* vx at (i+1/2, j) */
+                double d1 = S(sxx[IX2(j, i + 1)] - sxx[q]);
+                double d2 = S(sxy_hi(G, sxy, j, i) - sxy_lo(G, sxy, j, i));
+                double g = S(w * S(d1 + d2));
+                double bb = S(0.5 * S(B[q] + B[IX2(j, i + 1)]));
+                update(A, &vx[q], CP(c[0], q), S(bb * g));
+            }
+            if (j < ny - 1) {   /* vy at (i, j+1/2) */
+                double d1 = S(sxy[q] - sxy[IX2(j, i - 1)]);
+                double d2 = S(syy[IX2(j + 1, i)] - syy[q]);
+                double g = S(w * S(d1 + d2));
+                double bb = S(0.5 * S(B[q] + B[IX2(j + 1, i)]));
+                double inc = S(bb * g);
+                /* the s^{vy} source of Eq. A1 acts on the velocity itself,
+                 * after the division by rho; the sample is held in the
+                 * stencil format */
+                if (q == src_q)
+                    inc = S(inc + S(src_val));
+                update(A, &vy[q], CP(c[1], q), inc);
+            }
+        }
+
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
+    for (long j = 0; j < ny; ++j)
+        for (long i = 0; i < nx; ++i) {
+            long q = j * nx + i;
+            int surface = j == 0 || j == ny - 1;
+            double ex = S(w * S(vx[q] - vx[IX2(j, i - 1)]));
+            double ey = surface ? 0.0 : S(w * S(vy[q] - vy[IX2(j - 1, i)]));
+            double l2m = G->l2m[q], lam = G->lam[q];
+            update(A, &sxx[q], CP(c[2], q), S(S(l2m * ex) + S(lam * ey)));
+            if (!surface)
+                update(A, &syy[q], CP(c[3], q), S(S(l2m * ey) + S(lam * ex)));
+            if (j < ny - 1) {   /* sxy at (i+1/2, j+1/2) */
+                double a1 = S(vy[IX2(j, i + 1)] - vy[q]);
+                double a2 = S(vx[IX2(j + 1, i)] - vx[q]);
+                double g = S(w * S(a1 + a2));
+                update(A, &sxy[q], CP(c[4], q), S(G->mxy[q] * g));
+            }
+        }
+#undef CP
+#undef S
+}
+
+/* Discrete energy of the state (v^{n-1/2}, sigma^n), fp64:
+ *   E^n = dx^2/2 * sum_i [ sum_j h_j ( vx^- vx^+ / bx + s^T C^{-1} s )
+ *                        + sum_{j < ny-1} ( vy^- vy^+ / by + sxy^2 / mu_xy ) ]
+ * with h_j = 1/2 on the two surface rows and 1 elsewhere, v^+ recomputed in
+ * fp64 from the state (no source term), and C the 2x2 stiffness
+ * [[l2m, lam], [lam, l2m]] of the normal stresses, so
+ *   s^T C^{-1} s = (l2m (sxx^2 + syy^2) - 2 lam sxx syy) / (l2m^2 - lam^2)
+ * (on a surface row lam = 0 and syy = 0, leaving sxx^2 / l2m). */
+static double el2d_energy(const el2d *G, double dx, double *const *f)
+{
+    const long nx = G->nx, ny = G->ny;
+    const double w = G->w;
+    const double *vx = f[0], *vy = f[1], *sxx = f[2], *syy = f[3], *sxy = f[4];
+    const double *B = G->b;
+    double *rows = malloc(sizeof(double) * 2 * ny);
+#pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN)
+    for (long j = 0; j < ny; ++j) {
+        nsum acc = {0.0, 0.0};
+        const double h = (j == 0 || j == ny - 1) ? 0.5 : 1.0;
+        for (long i = 0; i < nx; ++i) {
+            long q = j * nx + i;
+            double gx = w * ((sxx[IX2(j, i + 1)] - sxx[q]) +
+                             (sxy_hi(G, sxy, j, i) - sxy_lo(G, sxy, j, i)));
+            double bx = 0.5 * (B[q] + B[IX2(j, i + 1)]);
+            double vxp = vx[q] + bx * gx;
+            double l2m = G->l2m[q], lam = G->lam[q];
+            double en = (l2m * (sxx[q] * sxx[q] + syy[q] * syy[q]) -
+                         2.0 * lam * (sxx[q] * syy[q])) /
+                        (l2m * l2m - lam * lam);
+            double e = h * ((vx[q] * vxp) / bx + en);
+            if (j < ny - 1) {
+                double gy = w * ((sxy[q] - sxy[IX2(j, i - 1)]) +
+                                 (syy[IX2(j + 1, i)] - syy[q]));
+                double by = 0.5 * (B[q] + B[IX2(j + 1, i)]);
+                double vyp = vy[q] + by * gy;
+                e = e + ((vy[q] * vyp) / by + (sxy[q] * sxy[q]) / G->mxy[q]);
+            }
+            nsum_add(&acc, e);
+        }
+        rows[2 * j] = acc.s;
+        rows[2 * j + 1] = acc.c;
+    }
+    nsum tot = {0.0, 0.0};
+    for (long j = 0; j < ny; ++j) {
+        nsum_add(&tot, rows[2 * j]);
+        nsum_add(&tot, rows[2 * j + 1]);
+    }
+    free(rows);
+    return 0.5 * dx * dx * (tot.s + tot.c);
+}
+
+/* Run nsteps of the 2D elastic free-surface system in place.  fields[5]
+ * and comps[5] (comps may be NULL when comp == COMP_NONE) are [ny][nx]
+ * arrays in the order vx, vy, sxx, syy, sxy; material rho, lambda, mu at
+ * cells.  Requires ny >= 3, syy zero on both surface rows and vy, sxy zero
+ * on row ny-1.  Point source: step n adds src[n] (n < nsrc) to vy at
+ * (src_x, src_y + 1/2), src_y <= ny-2.  Receivers: after step n, the five
+ * fields at cell (rec_x[r], rec_y[r]) go to rec_out[(n*nrec + r)*5 + f].
+ * The stencil format is fp64 or fp32.  Returns 0, or -1 on bad arguments. */
+int orc_elastic2d(long nx, long ny, double dx, double dt, const double *rho,
+                  const double *lam, const double *mu, double *const *fields,
+                  double *const *comps, int storage, int stencil, int comp,
+                  long nsteps, long energy_every, double *energy, int nthreads,
+                  long src_x, long src_y, const double *src, long nsrc,
+                  long nrec, const long *rec_x, const long *rec_y,
+                  double *rec_out)
+{
+    if (nx < 1 || ny < 3 || nsteps < 0 ||
+        (stencil != FMT_F64 && stencil != FMT_F32))
+        return -1;
+    double *none[EL2D_NF] = {0};
+    if (comp != COMP_NONE) {
+        if (!comps)
+            return -1;
+        for (int f = 0; f < EL2D_NF; ++f)
+            if (!comps[f])
+                return -1;
+    } else {
+        comps = none;
+    }
+    for (long i = 0; i < nx; ++i)
+        if (fields[3][i] != 0.0 || fields[3][(ny - 1) * nx + i] != 0.0 ||
+            fields[1][(ny - 1) * nx + i] != 0.0 ||
+            fields[4][(ny - 1) * nx + i] != 0.0)
+            return -1;
+    if (nsrc > 0 && (!src || src_x < 0 || src_x >= nx || src_y < 0 ||
+                     src_y > ny - 2))
+        return -1;
+    if (nrec > 0 && (!rec_x || !rec_y || !rec_out))
+        return -1;
+    for (long r = 0; r < nrec; ++r)
+        if (rec_x[r] < 0 || rec_x[r] >= nx || rec_y[r] < 0 || rec_y[r] >= ny)
+            return -1;
+    set_threads(nthreads);
+    el2d G;
+    el2d_setup(&G, nx, ny, dx, dt, rho, lam, mu);
+    arith A = {stencil, storage, comp};
+    long m = 0;
+    if (energy_every > 0)
+        energy[m++] = el2d_energy(&G, dx, fields);
+    for (long n = 1; n <= nsteps; ++n) {
+        const long src_q = n - 1 < nsrc ? src_y * nx + src_x : -1;
+        el2d_step(&G, &A, fields, comps, src_q, src_q >= 0 ? src[n - 1] : 0.0);
+        for (long r = 0; r < nrec; ++r) {
+            const long q = rec_y[r] * nx + rec_x[r];
+            for (int f = 0; f < EL2D_NF; ++f)
+                rec_out[((n - 1) * nrec + r) * EL2D_NF + f] = fields[f][q];
+        }
+        if (energy_every > 0 && n % energy_every == 0)
+            energy[m++] = el2d_energy(&G, dx, fields);
+    }
+    el2d_free(&G);
+    return 0;
+}
+
+double orc_elastic2d_energy(long nx, long ny, double dx, double dt,
+                            const double *rho, const double *lam,
+                            const double *mu, double *const *fields)
+{
+    if (nx < 1 || ny < 3)
+        return NAN;
+    el2d G;
+    el2d_setup(&G, nx, ny, dx, dt, rho, lam, mu);
+    double e = el2d_energy(&G, dx, fields);
+    el2d_free(&G);
+    return e;
+}
+
+#undef IX2
