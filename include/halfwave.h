@@ -11,6 +11,9 @@
  *     in both directions, 2nd-order staggered leapfrog in time;
  *   - the 3D velocity-stress elastic system, the 3D form of Eq. (A1)
  *     (App. A), 2nd order, on the standard staggered layout, periodic;
+ *   - the 2D velocity-stress elastic system of Eq. (A1) (App. A), 2nd
+ *     order, periodic in x and bounded in y by two free surfaces, with the
+ *     point source on the vertical velocity (the s^{vy} term);
  *   - per step and per field, the update of Alg. 1 (plain, V += R) or of
  *     Alg. 2 (compensated, Sec. 4) with the 3-operation sum (Code 1) or the
  *     6-operation sum (Code 2), the fields and compensation terms held in
@@ -23,17 +26,31 @@
  * (i dx, (j+1/2) dx).  3D arrays are [nz][ny][nx]; normal stresses and the
  * material at (i, j, k), vx at (i+1/2, j, k), vy at (i, j+1/2, k), vz at
  * (i, j, k+1/2), sxy at (i+1/2, j+1/2, k), sxz at (i+1/2, j, k+1/2), syz at
- * (i, j+1/2, k+1/2).  All indices wrap periodically.  The state at the top of
- * a step is (v^{n-1/2}, p^n) (or sigma^n): velocities are updated first.
+ * (i, j+1/2, k+1/2).  All indices wrap periodically, except y of the 2D
+ * elastic system.  The state at the top of a step is (v^{n-1/2}, p^n) (or
+ * sigma^n): velocities are updated first.
+ *
+ * 2D elastic layout ([ny][nx]): sxx, syy and the material at (i, j), vx at
+ * (i+1/2, j), vy at (i, j+1/2), sxy at (i+1/2, j+1/2); x wraps.  Rows 0 and
+ * ny-1 of the normal stresses are free surfaces (zero traction): syy is
+ * zero there and never updated; sxy half a cell outside a surface is minus
+ * sxy half a cell inside; on the surface rows sxx changes by the plate
+ * modulus 4 mu (lambda + mu) / (lambda + 2 mu) times the horizontal strain
+ * rate (the vertical strain rate eliminated through syy = 0).  vy and sxy
+ * live on rows 0 .. ny-2; their row ny-1 lies outside the body, is zero and
+ * stays zero.  ny >= 3.
  *
  * Field order:     acoustic  {vx, vy, p}
  *                  elastic   {vx, vy, vz, sxx, syy, szz, sxy, sxz, syz}
+ *                  elastic2d {vx, vy, sxx, syy, sxy}
  * Material order:  acoustic  {rho, kappa} at p points, kappa = 1/beta
- *                  elastic   {rho, lambda, mu} at cell centres
+ *                  elastic, elastic2d  {rho, lambda, mu} at cell centres
  * The material is used as fp32 values b = fp32(1/rho), kappa, lambda, mu;
  * staggered buoyancy is the mean of the two adjacent b, the shear modulus on
- * an edge the mean of the four adjacent mu.  dt and dx enter through the
- * stencil weights w_k = fp32(c_k * (dt/dx)).
+ * an edge the mean of the four adjacent mu (2D elastic: fp32 of the fp64
+ * mean; lambda + 2 mu, lambda and the plate modulus likewise rounded once
+ * from fp64).  dt and dx enter through the stencil weights
+ * w_k = fp32(c_k * (dt/dx)).
  *
  * Memory.  The library allocates no device memory.  The caller provides one
  * device buffer (the arena) per plan, at least hw_footprint() bytes, 256-byte
@@ -57,7 +74,7 @@
 extern "C" {
 #endif
 
-#define HW_ABI_VERSION 5u
+#define HW_ABI_VERSION 6u
 
 typedef enum hw_status {
     HW_OK = 0,
@@ -70,7 +87,7 @@ typedef enum hw_status {
     HW_E_STATE = 7       /* call out of order (e.g. advance before upload)   */
 } hw_status;
 
-enum hw_physics { HW_ACOUSTIC2D = 0, HW_ELASTIC3D = 1 };
+enum hw_physics { HW_ACOUSTIC2D = 0, HW_ELASTIC3D = 1, HW_ELASTIC2D = 2 };
 enum hw_storage { HW_F32 = 0, HW_F16 = 1, HW_BF16 = 2 };
 /* HW_COMP_TWOSUM8: the 6-operation sum with the compensation term held in
  * an 8-bit word instead of a value of the storage format: the TwoSum error t
@@ -104,7 +121,7 @@ typedef struct hw_problem {
     double dx;             /* grid spacing, all axes, > 0                     */
     double dt;             /* time step, > 0                                  */
     int64_t trace_cap;     /* energy samples reserved in the arena, >= 0      */
-    /* Point source and receivers (acoustic only; 0 for elastic): */
+    /* Point source and receivers (acoustic and 2D elastic; 0 for 3D): */
     int64_t src_cap;       /* source samples reserved in the arena, >= 0      */
     int32_t rec_cap;       /* receivers reserved, 0 .. 64                     */
     int32_t stencil;       /* enum hw_stencil (acoustic only; 0 for elastic)  */
@@ -119,7 +136,8 @@ uint32_t hw_abi_version(void);
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *hw_last_error(void);
 
-/* Number of fields (3 acoustic, 9 elastic) and material arrays (2, 3). */
+/* Number of fields (3 acoustic, 9 elastic, 5 elastic2d) and material
+ * arrays (2, 3, 3). */
 int32_t hw_num_fields(int32_t physics);
 int32_t hw_num_materials(int32_t physics);
 
@@ -128,8 +146,8 @@ int32_t hw_num_materials(int32_t physics);
 hw_status hw_footprint(const hw_problem *pb, size_t *device_bytes);
 
 /* Stability bound on the Courant number c_eff*dt/dx for this physics and
- * order: 1/sqrt(2) (2D, order 2), 1/(sqrt(2)*(9/8+1/24)) (2D, order 4),
- * 1/sqrt(3) (3D).  Returns a negative value for invalid arguments. */
+ * order: 1/sqrt(2) (2D, order 2, acoustic or elastic), 1/(sqrt(2)*(9/8+1/24))
+ * (2D, order 4), 1/sqrt(3) (3D).  Returns a negative value for invalid arguments. */
 double hw_cfl_bound(int32_t physics, int32_t order);
 
 /* Create a plan: validate *pb and carve the arena.  Host only, no HIP call.
@@ -145,7 +163,8 @@ void hw_plan_destroy(hw_plan *plan);
 /* Upload the material: hw_num_materials() host fp64 arrays, in the material
  * order above, each of nx*ny*nz values.  Validates on the host first: all
  * values finite, rho > 0, kappa > 0 (acoustic), mu > 0 and
- * 3 lambda + 2 mu > 0 (elastic), the fp32 values finite, and the Courant
+ * 3 lambda + 2 mu > 0 (elastic), mu > 0 and lambda + mu > 0 (elastic2d),
+ * the fp32 values finite, and the Courant
  * number below hw_cfl_bound() (HW_E_INVAL / HW_E_UNSTABLE).  The Courant
  * number uses, for every cell face, the staggered buoyancy of the face times
  * the larger modulus (kappa, or lambda + 2 mu) of the two cells it joins.
@@ -156,8 +175,10 @@ hw_status hw_set_material(hw_plan *plan, const double *const *material,
 /* Upload the initial state: hw_num_fields() host fp64 arrays in the field
  * order above (a NULL entry means all zeros).  Each value times
  * 2^scale_log2 must be finite and within the storage format's largest
- * finite value (HW_E_RANGE); it is rounded to nearest-even.  Compensation
- * terms, step counter and energy trace are reset.  Async on `stream`. */
+ * finite value (HW_E_RANGE); it is rounded to nearest-even.  2D elastic:
+ * syy on rows 0 and ny-1 and vy, sxy on row ny-1 must be zero (HW_E_INVAL).
+ * Compensation terms, step counter and energy trace are reset.  Async on
+ * `stream`. */
 hw_status hw_set_fields(hw_plan *plan, const double *const *fields,
                         void *stream);
 
@@ -173,8 +194,14 @@ hw_status hw_advance(hw_plan *plan, int64_t nsteps, int64_t energy_every,
  * (fp64, of the stored state (v^{n-1/2}, p^n)):
  *   acoustic  E = dx^2/2 * sum[ p^2/kappa + vx^- vx^+ / bx + vy^- vy^+ / by ]
  *   elastic   E = dx^3/2 * sum[ v^- . v^+ / b + s_n^T C^-1 s_n + s_ij^2/mu_ij ]
+ *   elastic2d E = dx^2/2 * sum_i[ sum_j h_j (vx^- vx^+ / bx + s_n^T C^-1 s_n)
+ *                                + sum_{j<ny-1} (vy^- vy^+ / by + sxy^2/mu_xy) ]
  * where v^+ = v^- + b * (stencil of p or div sigma) is recomputed in fp64,
- * C = lambda 1 1^T + 2 mu I acts on the normal stresses.  A non-finite
+ * C = lambda 1 1^T + 2 mu I acts on the normal stresses (2D elastic: the
+ * 2x2 [[l2m, lam], [lam, l2m]] with l2m = lambda + 2 mu and lam = lambda,
+ * on the surface rows l2m = the plate modulus and lam = 0), h_j = 1/2 on
+ * the two surface rows and 1 elsewhere; this energy is conserved exactly by
+ * the scheme in exact arithmetic.  A non-finite
  * energy sets the plan's sticky HW_E_NONFINITE, reported by hw_energy_trace
  * and hw_get_fields. */
 hw_status hw_record_energy(hw_plan *plan, void *stream);
@@ -203,24 +230,29 @@ hw_status hw_get_fields(hw_plan *plan, double *const *fields,
  * A plan with a source, receivers or a non-default stencil steps with
  * kernel shape 0 whatever its hw_plan_set_tile setting (the shapes give
  * identical bits).
- * HW_E_INVAL for elastic plans or a cell outside the grid,
+ * 2D elastic plans: the source acts on vy at (ix, iy+1/2), 0 <= iy <= ny-2
+ * (the s^{vy} term of Eq. A1): the sample is added to the velocity
+ * increment after the multiplication by the staggered buoyancy.
+ * HW_E_INVAL for 3D elastic plans or a cell outside the grid,
  * HW_E_NOMEM if nsamples > src_cap.  Synchronises `stream` (the samples are
  * copied before the call returns). */
 hw_status hw_set_source(hw_plan *plan, int64_t ix, int64_t iy,
                         const double *samples, int64_t nsamples, void *stream);
 
 /* Receivers: after each step n < rec_steps the new pressure p^{n+1} and
- * velocities vx^{n+1/2}, vy^{n+1/2} at each of the n cells (ix[r], iy[r])
- * are recorded in fp64 (exact widening, unscaled); row n of the trace
+ * velocities vx^{n+1/2}, vy^{n+1/2} (2D elastic: the five new fields) at
+ * each of the n cells (ix[r], iy[r]) are recorded in fp64 (exact widening,
+ * unscaled); row n of the trace
  * belongs to step n, counted as for hw_set_source.  0 <= n <= rec_cap
  * (HW_E_NOMEM), cells inside the grid (HW_E_INVAL).  n = 0 removes the
  * receivers.  Synchronises `stream`. */
 hw_status hw_set_receivers(hw_plan *plan, int32_t n, const int64_t *ix,
                            const int64_t *iy, void *stream);
 
-/* Copy the receiver trace to the host: out[(k*n + r)*3 + {0, 1, 2}] =
- * (p, vx, vy) of receiver r after step k, for k < min(cap_rows, rows), n the
- * receiver count; *rows_out = rows recorded (min(step, rec_steps)).
+/* Copy the receiver trace to the host: out[(k*n + r)*m + {0, 1, 2}] =
+ * (p, vx, vy) of receiver r after step k (m = 3; 2D elastic: m = 5 values
+ * in the field order), for k < min(cap_rows, rows), n the receiver count;
+ * *rows_out = rows recorded (min(step, rec_steps)).
  * Synchronises `stream`. */
 hw_status hw_receiver_trace(hw_plan *plan, double *out, int64_t cap_rows,
                             int64_t *rows_out, void *stream);
@@ -244,7 +276,9 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  *               strip ty rows tall;
  *   elastic3d   0 = two passes per step (velocities, then stresses), one
  *               plane per workgroup; 2 = one fused pass per step, a
- *               workgroup walks a tx by ty column through tz planes.
+ *               workgroup walks a tx by ty column through tz planes;
+ *   elastic2d   0 = two passes per step (velocities, then stresses), one
+ *               tx by ty tile per workgroup.
  * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
  * results.  Any of the output pointers may be NULL. */
 int32_t hw_tile_count(int32_t physics);

@@ -21,16 +21,18 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhalfwave.so")
 
-ACOUSTIC2D, ELASTIC3D = 0, 1
+ACOUSTIC2D, ELASTIC3D, ELASTIC2D = 0, 1, 2
+PHYSICS = {"acoustic2d": ACOUSTIC2D, "elastic3d": ELASTIC3D, "elastic2d": ELASTIC2D}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 COMP = {"none": 0, "fast2sum": 1, "twosum": 2, "twosum8": 3}
 STENCIL = {"f32": 0, "storage": 1, "f64": 2}
 ACOUSTIC_FIELDS = ("vx", "vy", "p")
 ELASTIC_FIELDS = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
+ELASTIC2D_FIELDS = ("vx", "vy", "sxx", "syy", "sxy")
 STATUS = {0: "HW_OK", 1: "HW_E_INVAL", 2: "HW_E_UNSTABLE", 3: "HW_E_RANGE",
           4: "HW_E_NOMEM", 5: "HW_E_DEVICE", 6: "HW_E_NONFINITE",
           7: "HW_E_STATE"}
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class HalfwaveError(RuntimeError):
@@ -149,7 +151,7 @@ def _f64_ptrs(arrays, n, shape, allow_none):
 @dataclass
 class Problem:
     """Mirror of hw_problem (see include/halfwave.h)."""
-    physics: str                  # 'acoustic2d' or 'elastic3d'
+    physics: str                  # 'acoustic2d', 'elastic3d' or 'elastic2d'
     nx: int
     ny: int
     nz: int = 1
@@ -160,14 +162,14 @@ class Problem:
     dt: float = 0.5
     scale_log2: int = 0
     trace_cap: int = 0
-    src_cap: int = 0              # point-source samples reserved (acoustic)
-    rec_cap: int = 0              # receivers reserved (acoustic, <= 64)
+    src_cap: int = 0              # point-source samples reserved (2D)
+    rec_cap: int = 0              # receivers reserved (2D, <= 64)
     rec_steps: int = 0            # receiver trace rows reserved
     stencil: str = "f32"          # stencil precision: 'f32', 'storage', 'f64'
 
     def c(self) -> _Problem:
         return _Problem(ABI_VERSION,
-                        {"acoustic2d": ACOUSTIC2D, "elastic3d": ELASTIC3D}[self.physics],
+                        PHYSICS[self.physics],
                         self.order, STORAGE[self.storage], COMP[self.comp],
                         self.scale_log2, self.nx, self.ny, self.nz, self.dx,
                         self.dt, self.trace_cap, self.src_cap, self.rec_cap,
@@ -175,12 +177,13 @@ class Problem:
 
     @property
     def shape(self):
-        return (self.ny, self.nx) if self.physics == "acoustic2d" else \
-            (self.nz, self.ny, self.nx)
+        return (self.nz, self.ny, self.nx) if self.physics == "elastic3d" else \
+            (self.ny, self.nx)
 
     @property
     def field_names(self):
-        return ACOUSTIC_FIELDS if self.physics == "acoustic2d" else ELASTIC_FIELDS
+        return {"acoustic2d": ACOUSTIC_FIELDS, "elastic3d": ELASTIC_FIELDS,
+                "elastic2d": ELASTIC2D_FIELDS}[self.physics]
 
     @property
     def cells(self) -> int:
@@ -194,12 +197,12 @@ def footprint(pb: Problem) -> int:
 
 
 def cfl_bound(physics: str, order: int) -> float:
-    return lib().hw_cfl_bound({"acoustic2d": 0, "elastic3d": 1}[physics], order)
+    return lib().hw_cfl_bound(PHYSICS[physics], order)
 
 
 def tiles(physics: str):
     """Kernel shapes by index: (tx, ty, tz, kind) as hw_tile_info."""
-    ph = {"acoustic2d": 0, "elastic3d": 1}[physics]
+    ph = PHYSICS[physics]
     out = []
     for t in range(lib().hw_tile_count(ph)):
         v = [ctypes.c_int32() for _ in range(4)]
@@ -332,11 +335,13 @@ class Plan:
         self._nrec = len(cells)
 
     def receiver_trace(self, stream=None) -> np.ndarray:
-        """[rows, receivers, 3] array of (p, vx, vy) after each step."""
+        """[rows, receivers, m] array after each step: (p, vx, vy), m = 3;
+        2D elastic: the five fields in field order, m = 5."""
         nrec = getattr(self, "_nrec", 0)
         rows = ctypes.c_int64()
         cap = max(self.pb.rec_steps, 1)
-        out = np.zeros((cap, max(nrec, 1), 3))
+        m = 5 if self.pb.physics == "elastic2d" else 3
+        out = np.zeros((cap, max(nrec, 1), m))
         _check(lib().hw_receiver_trace(self.handle,
                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        cap, ctypes.byref(rows), self._s(stream)))

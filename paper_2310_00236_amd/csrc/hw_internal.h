@@ -49,6 +49,30 @@ struct El3dDesc {
     void *f[2][9];                // vx vy vz sxx syy szz sxy sxz syz
 };
 
+// Device-resident description of one 2D elastic plan (periodic in x, free
+// surfaces on rows 0 and ny-1); same word layout and ping-pong as above.
+// The material arrives as the per-cell fp32 coefficients of the step: b =
+// 1/rho; l2m = lambda + 2 mu and lam = lambda, except on the surface rows
+// where l2m is the plate modulus and lam = 0; mxy = the shear modulus at the
+// sxy point (i+1/2, j+1/2), the mean of the four cells around it.
+struct El2dDesc {
+    int64_t nx, ny, pitch;
+    float w;                      // dt/dx (fp32)
+    const float *b, *l2m, *lam, *mxy;
+    void *f[2][5];                // vx vy sxx syy sxy
+    // point source on vy and receivers, as for Ac2dDesc (trace rows hold
+    // the five fields)
+    const int64_t *step;
+    const float *src;
+    int64_t src_n;
+    int32_t src_x, src_y;
+    int32_t rec_n;
+    const int32_t *rec_xy;
+    double *rec;
+    int64_t rec_rows;
+    double rec_scale;
+};
+
 // Arguments of one batched launch: the shots it covers, the parity (which
 // field set is current) of each, the first global tile of each shot and
 // its tile counts along x and y (for the launch's tile shape; 3D shots have
@@ -94,8 +118,12 @@ constexpr TileShape kTiles2D[] = {{64, 16, 0, 1}, {64, 32, 0, 1}, {128, 16, 0, 1
 constexpr TileShape kTiles3D[] = {{64, 4, 0, 1},    {256, 1, 0, 1},   {64, 6, 2, 128},
                                   {64, 6, 2, 64},   {64, 6, 2, 512},  {64, 10, 2, 128},
                                   {64, 14, 2, 128}};
+// 2D elastic: two passes (velocities, then stresses), one 64 x 4 tile per
+// workgroup
+constexpr TileShape kTilesEl2D[] = {{64, 4, 0, 1}};
 constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
 constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
+constexpr int kNumTilesEl2D = sizeof(kTilesEl2D) / sizeof(kTilesEl2D[0]);
 
 // Launchers (one translation unit per physics).
 // one: the host copy of the descriptor when the launch covers a single plan
@@ -117,6 +145,13 @@ hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
 hipError_t launch_el3d_step(const El3dBatch &a, const El3dDesc *one, int storage,
                             int comp, int tile, hipStream_t s);
 hipError_t launch_el3d_energy(const El3dDesc *d_desc, int parity, int64_t rows,
+                              int storage, int stride, double *partial,
+                              hipStream_t s);
+// One step of one 2D elastic plan (descriptor by value, field set parity
+// current); forced: the plan has a point source or receivers.
+hipError_t launch_el2d_step(const El2dDesc &d, int parity, int storage, int comp,
+                            bool forced, hipStream_t s);
+hipError_t launch_el2d_energy(const El2dDesc *d_desc, int parity, int64_t ny,
                               int storage, int stride, double *partial,
                               hipStream_t s);
 hipError_t launch_energy_finish(const double *partial, int64_t n,

@@ -62,6 +62,8 @@ double cfl_bound(int physics, int order)
     }
     if (physics == HW_ELASTIC3D && order == 2)
         return 1.0 / std::sqrt(3.0);
+    if (physics == HW_ELASTIC2D && order == 2)
+        return 1.0 / std::sqrt(2.0);
     return -1.0;
 }
 
@@ -74,7 +76,8 @@ struct Layout {
     size_t comp_off = 0;           // their offset after each value array
     size_t field_bytes = 0, mat_bytes = 0;
     size_t off_fld[2][9] = {};
-    size_t off_mat[3] = {}, off_staging = 0, off_partial = 0, off_trace = 0;
+    size_t off_mat[4] = {}, off_staging = 0, off_partial = 0, off_trace = 0;
+    int rec_vals = 3;              // values per receiver and trace row
     size_t off_flags = 0, off_desc = 0, total = 0;
     size_t off_src = 0, off_recxy = 0, off_rec = 0;
 };
@@ -85,7 +88,8 @@ hw_status validate(const hw_problem *pb)
         return fail(HW_E_INVAL, "problem is NULL");
     if (pb->abi_version != HW_ABI_VERSION)
         return fail(HW_E_INVAL, "abi_version mismatch");
-    if (pb->physics != HW_ACOUSTIC2D && pb->physics != HW_ELASTIC3D)
+    if (pb->physics != HW_ACOUSTIC2D && pb->physics != HW_ELASTIC3D &&
+        pb->physics != HW_ELASTIC2D)
         return fail(HW_E_INVAL, "unknown physics");
     if (cfl_bound(pb->physics, pb->order) < 0)
         return fail(HW_E_INVAL, "unsupported order for this physics");
@@ -101,8 +105,11 @@ hw_status validate(const hw_problem *pb)
         return fail(HW_E_INVAL, "scale_log2 out of [-60, 60]");
     if (pb->nx < 1 || pb->ny < 1 || pb->nz < 1)
         return fail(HW_E_INVAL, "grid sizes must be >= 1");
-    if (pb->physics == HW_ACOUSTIC2D && pb->nz != 1)
-        return fail(HW_E_INVAL, "nz must be 1 for acoustic2d");
+    if (pb->physics != HW_ELASTIC3D && pb->nz != 1)
+        return fail(HW_E_INVAL, "nz must be 1 for 2D problems");
+    if (pb->physics == HW_ELASTIC2D && pb->ny < 3)
+        return fail(HW_E_INVAL, "elastic2d needs ny >= 3 (two free surfaces "
+                                "and an interior row)");
     const double lim = 1u << 30;
     if ((double)pb->nx > lim || (double)pb->ny > lim || (double)pb->nz > lim ||
         (double)pb->nx * pb->ny * pb->nz > 0x1p40)
@@ -118,11 +125,11 @@ hw_status validate(const hw_problem *pb)
                                 "[0, 64]");
     if (pb->stencil < HW_STENCIL_F32 || pb->stencil > HW_STENCIL_F64)
         return fail(HW_E_INVAL, "unknown stencil precision");
-    if (pb->physics != HW_ACOUSTIC2D &&
-        (pb->src_cap != 0 || pb->rec_cap != 0 || pb->rec_steps != 0 ||
-         pb->stencil != HW_STENCIL_F32))
-        return fail(HW_E_INVAL, "sources, receivers and stencil precisions "
-                                "are acoustic only");
+    if (pb->physics == HW_ELASTIC3D &&
+        (pb->src_cap != 0 || pb->rec_cap != 0 || pb->rec_steps != 0))
+        return fail(HW_E_INVAL, "sources and receivers are 2D only");
+    if (pb->physics != HW_ACOUSTIC2D && pb->stencil != HW_STENCIL_F32)
+        return fail(HW_E_INVAL, "stencil precisions are acoustic only");
     if ((double)pb->src_cap > 0x1p40 ||
         (double)pb->rec_steps * (double)pb->rec_cap > 0x1p36)
         return fail(HW_E_INVAL, "source or receiver capacity too large");
@@ -142,8 +149,11 @@ Layout make_layout(const hw_problem *pb)
 {
     Layout L;
     const bool ac = pb->physics == HW_ACOUSTIC2D;
-    L.nf = ac ? 3 : 9;
-    L.nm = ac ? 2 : 3;
+    const bool el2 = pb->physics == HW_ELASTIC2D;
+    L.nf = ac ? 3 : el2 ? 5 : 9;
+    // device material arrays (2D elastic: the four per-cell coefficients)
+    L.nm = ac ? 2 : el2 ? 4 : 3;
+    L.rec_vals = el2 ? 5 : 3;
     L.sets = 2;
     L.pitch = (pb->nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
     L.slab = L.pitch * pb->ny;
@@ -181,9 +191,10 @@ Layout make_layout(const hw_problem *pb)
     L.off_recxy = off;
     off += align_up((size_t)pb->rec_cap * 8, kAlign);
     L.off_rec = off;
-    off += align_up((size_t)pb->rec_steps * pb->rec_cap * 3 * 8, kAlign);
+    off += align_up((size_t)pb->rec_steps * pb->rec_cap * L.rec_vals * 8, kAlign);
     L.off_desc = off;
-    off += align_up(std::max(sizeof(Ac2dDesc), sizeof(El3dDesc)), kAlign);
+    off += align_up(std::max({sizeof(Ac2dDesc), sizeof(El3dDesc), sizeof(El2dDesc)}),
+                    kAlign);
     L.total = off;
     return L;
 }
@@ -204,12 +215,13 @@ struct hw_plan {
     Layout L;
     char *arena;
     void *fld[2][9];
-    float *mat[3];
+    float *mat[4];
     double *staging, *partial, *trace;
     int32_t *flags;
     void *d_desc;
     Ac2dDesc h2;
     El3dDesc h3;
+    El2dDesc he;
     int cur = 0;
     int64_t step = 0;
     int64_t trace_n = 0;
@@ -219,7 +231,11 @@ struct hw_plan {
     int tile = 0;
     double scale_up = 1.0, scale_down = 1.0;
     int64_t *counter = nullptr;    // device step counter (sources, receivers)
-    bool counts() const { return h2.src_n > 0 || h2.rec_n > 0; }
+    bool counts() const
+    {
+        return pb.physics == HW_ELASTIC2D ? he.src_n > 0 || he.rec_n > 0
+                                          : h2.src_n > 0 || h2.rec_n > 0;
+    }
     // captured run of kGraphSteps steps starting from field set 0
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
@@ -238,11 +254,25 @@ namespace {
 
 hipStream_t S(void *s) { return (hipStream_t)s; }
 
-int num_tiles(const hw_problem &pb) { return pb.physics == HW_ACOUSTIC2D ? kNumTiles2D : kNumTiles3D; }
+const TileShape *tile_table(int physics)
+{
+    return physics == HW_ACOUSTIC2D ? kTiles2D : physics == HW_ELASTIC3D ? kTiles3D
+                                                                           : kTilesEl2D;
+}
+
+int tile_count(int physics)
+{
+    return physics == HW_ACOUSTIC2D ? kNumTiles2D
+           : physics == HW_ELASTIC3D ? kNumTiles3D
+           : physics == HW_ELASTIC2D ? kNumTilesEl2D
+                                     : 0;
+}
+
+int num_tiles(const hw_problem &pb) { return tile_count(pb.physics); }
 
 void tile_counts(const hw_plan *p, int tile, int32_t *tx, int32_t *ty, int32_t *total)
 {
-    const TileShape t = p->pb.physics == HW_ACOUSTIC2D ? kTiles2D[tile] : kTiles3D[tile];
+    const TileShape t = tile_table(p->pb.physics)[tile];
     *tx = (int32_t)((p->pb.nx + t.tx - 1) / t.tx);
     *ty = (int32_t)((p->pb.ny + t.ty - 1) / t.ty);
     *total = *tx * *ty * (int32_t)((p->pb.nz + t.tz - 1) / t.tz);
@@ -260,6 +290,32 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
                            const int *parity, hipStream_t s)
 {
     const hw_plan *p0 = plans[0];
+    if (p0->pb.physics == HW_ELASTIC2D) {
+        // one launch pair per plan (descriptor by value); the plans with a
+        // source or receivers count their steps on the device afterwards
+        StepCounters c;
+        c.n = 0;
+        for (int i = 0; i < n; ++i) {
+            hw_plan *p = plans[i];
+            hipError_t e = launch_el2d_step(p->he, parity[i], p->pb.storage, p->pb.comp,
+                                            p->counts(), s);
+            if (e == hipSuccess && p->counts()) {
+                c.c[c.n++] = p->counter;
+                if (c.n == kMaxBatch) {
+                    e = launch_tick(c, s);
+                    c.n = 0;
+                }
+            }
+            if (e != hipSuccess)
+                return fail(HW_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
+        }
+        if (c.n > 0) {
+            hipError_t e = launch_tick(c, s);
+            if (e != hipSuccess)
+                return fail(HW_E_DEVICE, std::string("step launch: ") + hipGetErrorString(e));
+        }
+        return HW_OK;
+    }
     for (int base = 0; base < n; base += kMaxBatch) {
         const int m = std::min(kMaxBatch, n - base);
         hipError_t e;
@@ -490,6 +546,9 @@ hw_status record_energy(hw_plan *p, hipStream_t s)
         e = launch_ac2d_energy((const Ac2dDesc *)p->d_desc, p->cur, p->pb.ny,
                                p->pb.storage, p->pb.order, p->L.words,
                                p->partial, s);
+    } else if (p->pb.physics == HW_ELASTIC2D) {
+        e = launch_el2d_energy((const El2dDesc *)p->d_desc, p->cur, p->pb.ny,
+                               p->pb.storage, p->L.words, p->partial, s);
     } else {
         factor *= p->pb.dx;
         e = launch_el3d_energy((const El3dDesc *)p->d_desc, p->cur, p->L.rows,
@@ -531,6 +590,16 @@ hw_status check_ready(const hw_plan *p)
 
 hw_status host_fields_in_range(const hw_plan *p, const double *const *fields)
 {
+    if (p->pb.physics == HW_ELASTIC2D) {
+        // syy vanishes on the free surfaces; vy and sxy have no row ny-1
+        const int64_t nx = p->pb.nx, last = (p->pb.ny - 1) * nx;
+        for (int64_t i = 0; i < nx; ++i)
+            if ((fields[3] && (fields[3][i] != 0.0 || fields[3][last + i] != 0.0)) ||
+                (fields[1] && fields[1][last + i] != 0.0) ||
+                (fields[4] && fields[4][last + i] != 0.0))
+                return fail(HW_E_INVAL, "elastic2d: syy must be zero on rows 0 and "
+                                        "ny-1, vy and sxy zero on row ny-1");
+    }
     const double maxv = max_finite(p->pb.storage);
     for (int f = 0; f < p->L.nf; ++f) {
         const double *a = fields[f];
@@ -552,7 +621,8 @@ hw_status host_material_ok(const hw_plan *p, const double *const *mat)
 {
     const hw_problem &pb = p->pb;
     const int64_t nx = pb.nx, ny = pb.ny, nz = pb.nz, n = p->L.cells;
-    for (int m = 0; m < p->L.nm; ++m)
+    const int nin = pb.physics == HW_ACOUSTIC2D ? 2 : 3;   // host arrays
+    for (int m = 0; m < nin; ++m)
         if (!mat[m])
             return fail(HW_E_INVAL, "material array " + std::to_string(m) + " is NULL");
     for (int64_t i = 0; i < n; ++i) {
@@ -560,12 +630,18 @@ hw_status host_material_ok(const hw_plan *p, const double *const *mat)
         if (!std::isfinite(rho) || !(rho > 0) || !std::isfinite((float)(1.0 / rho)) ||
             (float)(1.0 / rho) == 0.0f)
             return fail(HW_E_INVAL, "rho must be finite, > 0 and 1/rho must fit fp32");
-        for (int m = 1; m < p->L.nm; ++m)
+        for (int m = 1; m < nin; ++m)
             if (!std::isfinite(mat[m][i]) || !std::isfinite((float)mat[m][i]))
                 return fail(HW_E_INVAL, "material values must be finite in fp32");
         if (pb.physics == HW_ACOUSTIC2D) {
             if (!(mat[1][i] > 0))
                 return fail(HW_E_INVAL, "kappa must be > 0");
+        } else if (pb.physics == HW_ELASTIC2D) {
+            // plane strain: positive shear and 2D bulk moduli (the plate
+            // modulus of the surface rows is then positive as well)
+            const double lam = mat[1][i], mu = mat[2][i];
+            if (!(mu > 0) || !(lam + mu > 0))
+                return fail(HW_E_INVAL, "need mu > 0 and lambda + mu > 0");
         } else {
             const double lam = mat[1][i], mu = mat[2][i];
             if (!(mu > 0) || !(3 * lam + 2 * mu > 0))
@@ -583,7 +659,7 @@ hw_status host_material_ok(const hw_plan *p, const double *const *mat)
             for (int64_t i = 0; i < nx; ++i) {
                 const int64_t q = idx(i, j, k);
                 const int64_t nb[3] = {idx(i + 1, j, k), idx(i, j + 1, k), idx(i, j, k + 1)};
-                const int naxes = pb.physics == HW_ACOUSTIC2D ? 2 : 3;
+                const int naxes = pb.physics == HW_ELASTIC3D ? 3 : 2;
                 for (int a = 0; a < naxes; ++a) {
                     const int64_t r = nb[a];
                     const double bf = 0.5 * (1.0 / mat[0][q] + 1.0 / mat[0][r]);
@@ -609,9 +685,13 @@ hw_status host_material_ok(const hw_plan *p, const double *const *mat)
 
 hw_status upload_desc(hw_plan *p, hipStream_t s)
 {
-    const void *src = p->pb.physics == HW_ACOUSTIC2D ? (const void *)&p->h2
-                                                      : (const void *)&p->h3;
-    const size_t n = p->pb.physics == HW_ACOUSTIC2D ? sizeof(Ac2dDesc) : sizeof(El3dDesc);
+    const int ph = p->pb.physics;
+    const void *src = ph == HW_ACOUSTIC2D ? (const void *)&p->h2
+                      : ph == HW_ELASTIC3D ? (const void *)&p->h3
+                                           : (const void *)&p->he;
+    const size_t n = ph == HW_ACOUSTIC2D ? sizeof(Ac2dDesc)
+                     : ph == HW_ELASTIC3D ? sizeof(El3dDesc)
+                                          : sizeof(El2dDesc);
     HW_HIP(hipMemcpyAsync(p->d_desc, src, n, hipMemcpyHostToDevice, s));
     return HW_OK;
 }
@@ -637,6 +717,17 @@ hw_status advance_one(hw_plan *p, int64_t nsteps, int64_t every, hipStream_t s)
     return HW_OK;
 }
 
+// Apply f to the descriptor that carries a 2D plan's source and receivers
+// (the acoustic and the 2D elastic descriptors name them alike).
+template <class F>
+void on_forcing(hw_plan *p, F f)
+{
+    if (p->pb.physics == HW_ELASTIC2D)
+        f(p->he);
+    else
+        f(p->h2);
+}
+
 struct BlobHeader {
     char magic[8];
     uint32_t abi;
@@ -657,12 +748,14 @@ const char *hw_last_error(void) { return g_error.c_str(); }
 
 int32_t hw_num_fields(int32_t physics)
 {
-    return physics == HW_ACOUSTIC2D ? 3 : physics == HW_ELASTIC3D ? 9 : 0;
+    return physics == HW_ACOUSTIC2D ? 3 : physics == HW_ELASTIC3D ? 9
+                                        : physics == HW_ELASTIC2D ? 5 : 0;
 }
 
 int32_t hw_num_materials(int32_t physics)
 {
-    return physics == HW_ACOUSTIC2D ? 2 : physics == HW_ELASTIC3D ? 3 : 0;
+    return physics == HW_ACOUSTIC2D ? 2
+           : physics == HW_ELASTIC3D || physics == HW_ELASTIC2D ? 3 : 0;
 }
 
 double hw_cfl_bound(int32_t physics, int32_t order) { return cfl_bound(physics, order); }
@@ -703,7 +796,7 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
             const int ss = s < L.sets ? s : 0;
             p->fld[s][f] = f < L.nf ? p->arena + L.off_fld[ss][f] : nullptr;
         }
-    for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 4; ++m)
         p->mat[m] = m < L.nm ? (float *)(p->arena + L.off_mat[m]) : nullptr;
     p->staging = (double *)(p->arena + L.off_staging);
     p->partial = (double *)(p->arena + L.off_partial);
@@ -729,6 +822,27 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
             d.p[s] = p->fld[s][2];
         }
         d.comp_off = (int64_t)L.comp_off;
+        p->counter = (int64_t *)(p->arena + L.off_flags + 8);
+        d.step = p->counter;
+        d.src = (const float *)(p->arena + L.off_src);
+        d.rec_xy = (const int32_t *)(p->arena + L.off_recxy);
+        d.rec = (double *)(p->arena + L.off_rec);
+        d.rec_rows = pb->rec_steps;
+        d.rec_scale = p->scale_down;
+    } else if (pb->physics == HW_ELASTIC2D) {
+        El2dDesc &d = p->he;
+        std::memset(&d, 0, sizeof(d));
+        d.nx = pb->nx;
+        d.ny = pb->ny;
+        d.pitch = L.pitch;
+        d.w = (float)(1.0 * r);
+        d.b = p->mat[0];
+        d.l2m = p->mat[1];
+        d.lam = p->mat[2];
+        d.mxy = p->mat[3];
+        for (int s = 0; s < 2; ++s)
+            for (int f = 0; f < 5; ++f)
+                d.f[s][f] = p->fld[s][f];
         p->counter = (int64_t *)(p->arena + L.off_flags + 8);
         d.step = p->counter;
         d.src = (const float *)(p->arena + L.off_src);
@@ -767,6 +881,40 @@ hw_status hw_set_material(hw_plan *p, const double *const *material, void *strea
         return st;
     hipStream_t s = S(stream);
     const int64_t nx = p->pb.nx;
+    if (p->pb.physics == HW_ELASTIC2D) {
+        // The step's per-cell coefficients, each computed in fp64 and
+        // rounded once to fp32 on the device: lambda + 2 mu and lambda, on
+        // the two surface rows the plate modulus 4 mu (lambda + mu) /
+        // (lambda + 2 mu) and 0 (syy = 0 eliminates the vertical strain
+        // rate); and mu at each sxy point, the mean of the four cells
+        // around it (rows 0 .. ny-2).
+        const int64_t ny = p->pb.ny, n = p->L.cells;
+        const double *lam = material[1], *mu = material[2];
+        std::vector<double> tab[3];
+        for (auto &t : tab)
+            t.assign((size_t)n, 0.0);
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t q = j * nx + i, qx = j * nx + (i + 1) % nx;
+                const bool surface = j == 0 || j == ny - 1;
+                tab[0][q] = surface ? (4.0 * mu[q] * (lam[q] + mu[q])) / (lam[q] + 2.0 * mu[q])
+                                    : lam[q] + 2.0 * mu[q];
+                tab[1][q] = surface ? 0.0 : lam[q];
+                if (j < ny - 1)
+                    tab[2][q] = 0.25 * ((mu[q] + mu[qx]) + (mu[q + nx] + mu[qx + nx]));
+            }
+        for (int m = 0; m < p->L.nm; ++m) {
+            const double *src = m == 0 ? material[0] : tab[m - 1].data();
+            HW_HIP(hipMemcpyAsync(p->staging, src, (size_t)n * 8, hipMemcpyHostToDevice, s));
+            HW_HIP(launch_material(p->staging, p->mat[m], m == 0, nx, p->L.rows,
+                                   p->L.pitch, s));
+        }
+        if ((st = upload_desc(p, s)) != HW_OK)
+            return st;
+        HW_HIP(hipStreamSynchronize(s));     // the tables are local
+        p->have_material = true;
+        return HW_OK;
+    }
     for (int m = 0; m < p->L.nm; ++m) {
         HW_HIP(hipMemcpyAsync(p->staging, material[m], (size_t)p->L.cells * 8,
                               hipMemcpyHostToDevice, s));
@@ -987,14 +1135,16 @@ hw_status hw_set_source(hw_plan *p, int64_t ix, int64_t iy, const double *sample
 {
     if (!p)
         return fail(HW_E_INVAL, "plan is NULL");
-    if (p->pb.physics != HW_ACOUSTIC2D)
-        return fail(HW_E_INVAL, "sources are acoustic only");
+    if (p->pb.physics == HW_ELASTIC3D)
+        return fail(HW_E_INVAL, "sources are 2D only");
     if (nsamples < 0 || (nsamples > 0 && !samples))
         return fail(HW_E_INVAL, "bad sample array");
     if (nsamples > p->pb.src_cap)
         return fail(HW_E_NOMEM, "more samples than src_cap");
     if (nsamples > 0 && (ix < 0 || ix >= p->pb.nx || iy < 0 || iy >= p->pb.ny))
         return fail(HW_E_INVAL, "source cell outside the grid");
+    if (nsamples > 0 && p->pb.physics == HW_ELASTIC2D && iy > p->pb.ny - 2)
+        return fail(HW_E_INVAL, "elastic2d: the vy source row must be <= ny-2");
     std::vector<float> v((size_t)nsamples);
     for (int64_t n = 0; n < nsamples; ++n) {
         if (!std::isfinite(samples[n]) || !std::isfinite((float)samples[n]))
@@ -1003,12 +1153,15 @@ hw_status hw_set_source(hw_plan *p, int64_t ix, int64_t iy, const double *sample
     }
     hipStream_t s = S(stream);
     HW_HIP(hipStreamSynchronize(s));
+    const float *dsrc = nullptr;
+    on_forcing(p, [&](auto &d) { dsrc = d.src; });
     if (nsamples > 0)
-        HW_HIP(hipMemcpy((void *)p->h2.src, v.data(), v.size() * 4,
-                         hipMemcpyHostToDevice));
-    p->h2.src_n = nsamples;
-    p->h2.src_x = (int32_t)(nsamples > 0 ? ix : 0);
-    p->h2.src_y = (int32_t)(nsamples > 0 ? iy : 0);
+        HW_HIP(hipMemcpy((void *)dsrc, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    on_forcing(p, [&](auto &d) {
+        d.src_n = nsamples;
+        d.src_x = (int32_t)(nsamples > 0 ? ix : 0);
+        d.src_y = (int32_t)(nsamples > 0 ? iy : 0);
+    });
     hw_status st = upload_desc(p, s);
     if (st == HW_OK && p->graph) {      // the captured launches hold the old descriptor
         (void)hipGraphExecDestroy(p->graph);
@@ -1024,8 +1177,8 @@ hw_status hw_set_receivers(hw_plan *p, int32_t n, const int64_t *ix, const int64
 {
     if (!p)
         return fail(HW_E_INVAL, "plan is NULL");
-    if (p->pb.physics != HW_ACOUSTIC2D)
-        return fail(HW_E_INVAL, "receivers are acoustic only");
+    if (p->pb.physics == HW_ELASTIC3D)
+        return fail(HW_E_INVAL, "receivers are 2D only");
     if (n < 0 || (n > 0 && (!ix || !iy)))
         return fail(HW_E_INVAL, "bad receiver arrays");
     if (n > p->pb.rec_cap)
@@ -1039,10 +1192,11 @@ hw_status hw_set_receivers(hw_plan *p, int32_t n, const int64_t *ix, const int64
     }
     hipStream_t s = S(stream);
     HW_HIP(hipStreamSynchronize(s));
+    const int32_t *dxy = nullptr;
+    on_forcing(p, [&](auto &d) { dxy = d.rec_xy; });
     if (n > 0)
-        HW_HIP(hipMemcpy((void *)p->h2.rec_xy, xy.data(), xy.size() * 4,
-                         hipMemcpyHostToDevice));
-    p->h2.rec_n = n;
+        HW_HIP(hipMemcpy((void *)dxy, xy.data(), xy.size() * 4, hipMemcpyHostToDevice));
+    on_forcing(p, [&](auto &d) { d.rec_n = n; });
     hw_status st = upload_desc(p, s);
     if (st == HW_OK && p->graph) {
         (void)hipGraphExecDestroy(p->graph);
@@ -1058,15 +1212,21 @@ hw_status hw_receiver_trace(hw_plan *p, double *out, int64_t cap_rows, int64_t *
 {
     if (!p)
         return fail(HW_E_INVAL, "plan is NULL");
-    if (p->pb.physics != HW_ACOUSTIC2D)
-        return fail(HW_E_INVAL, "receivers are acoustic only");
+    if (p->pb.physics == HW_ELASTIC3D)
+        return fail(HW_E_INVAL, "receivers are 2D only");
     const int64_t rows = std::min(p->step, p->pb.rec_steps);
     if (rows_out)
         *rows_out = rows;
     hipStream_t s = S(stream);
     const int64_t k = std::min(rows, std::max<int64_t>(cap_rows, 0));
-    if (out && k > 0 && p->h2.rec_n > 0)
-        HW_HIP(hipMemcpyAsync(out, p->h2.rec, (size_t)k * p->h2.rec_n * 3 * 8,
+    int32_t rn = 0;
+    const double *rec = nullptr;
+    on_forcing(p, [&](auto &d) {
+        rn = d.rec_n;
+        rec = d.rec;
+    });
+    if (out && k > 0 && rn > 0)
+        HW_HIP(hipMemcpyAsync(out, rec, (size_t)k * rn * p->L.rec_vals * 8,
                               hipMemcpyDeviceToHost, s));
     HW_HIP(hipStreamSynchronize(s));
     return HW_OK;
@@ -1074,7 +1234,7 @@ hw_status hw_receiver_trace(hw_plan *p, double *out, int64_t cap_rows, int64_t *
 
 int32_t hw_tile_count(int32_t physics)
 {
-    return physics == HW_ACOUSTIC2D ? kNumTiles2D : physics == HW_ELASTIC3D ? kNumTiles3D : 0;
+    return tile_count(physics);
 }
 
 hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx, int32_t *ty,
@@ -1082,7 +1242,7 @@ hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx, int32_t *ty,
 {
     if (tile < 0 || tile >= hw_tile_count(physics))
         return fail(HW_E_INVAL, "tile index out of range");
-    const TileShape t = physics == HW_ACOUSTIC2D ? kTiles2D[tile] : kTiles3D[tile];
+    const TileShape t = tile_table(physics)[tile];
     if (tx)
         *tx = t.tx;
     if (ty)

@@ -218,3 +218,52 @@ def test_source_and_receiver_validation_before_device():
     assert L.hw_set_source(h, 0, 0, s5.ctypes.data_as(P), 1, None) == 1
     assert L.hw_set_receivers(h, 1, ix.ctypes.data_as(P64), iy.ctypes.data_as(P64), None) == 1
     L.hw_plan_destroy(h)
+
+
+def test_elastic2d_problem_rules():
+    """The 2D elastic system (App. A, free surfaces): order 2, nz = 1,
+    ny >= 3, the fp32 stencil, 16-bit compensation words; sources and
+    receivers allowed, with five values per receiver and trace row."""
+    L = hw.lib()
+    assert L.hw_num_fields(2) == 5 and L.hw_num_materials(2) == 3
+    assert hw.cfl_bound("elastic2d", 2) == pytest.approx(2 ** -0.5)
+    assert L.hw_cfl_bound(2, 4) < 0
+    assert hw.tiles("elastic2d") == [(64, 4, 1, 0)]
+    e2 = dict(physics="elastic2d", order=2)
+    for kw in (dict(order=4), dict(nz=2), dict(ny=2), dict(stencil="f64"),
+               dict(stencil="storage"), dict(comp="twosum8")):
+        with pytest.raises(hw.HalfwaveError) as ei:
+            hw.footprint(_pb(**{**e2, **kw}))
+        assert ei.value.name == "HW_E_INVAL", kw
+    base = hw.footprint(_pb(**e2))
+    assert hw.footprint(_pb(**e2, rec_cap=3, rec_steps=100)) >= base + 3 * 100 * 5 * 8
+    assert hw.footprint(_pb(**e2, storage="f32", comp="none")) < \
+        hw.footprint(_pb(**e2, storage="f32", comp="twosum"))
+
+
+def test_elastic2d_host_validation_before_device():
+    P = ctypes.POINTER(ctypes.c_double)
+    L = hw.lib()
+    pb = _pb(physics="elastic2d", order=2, nx=12, ny=7, dt=0.1, src_cap=4,
+             rec_cap=1, rec_steps=4)
+    st, h = _plan(pb)
+    assert st == 0
+    one = np.ones((7, 12))
+    lam = one.copy()
+    lam[3, 4] = -1.5                # lambda + mu < 0
+    assert _set(L.hw_set_material, h, [one, lam, one]) == 1
+    mu = one.copy()
+    mu[0, 0] = 0.0
+    assert _set(L.hw_set_material, h, [one, one, mu]) == 1
+    assert _set(L.hw_set_material, h, [one, one, 40 * one]) == 2       # unstable
+    z = np.zeros((7, 12))
+    syy = z.copy()
+    syy[6, 3] = 0.5                 # syy on the bottom surface
+    assert _set(L.hw_set_fields, h, [None, None, None, syy, None]) == 1
+    vy = z.copy()
+    vy[6, 0] = 0.5                  # vy outside the body
+    assert _set(L.hw_set_fields, h, [None, vy, None, None, None]) == 1
+    assert b"elastic2d" in L.hw_last_error()
+    s1 = np.ones(1)
+    assert L.hw_set_source(h, 3, 6, s1.ctypes.data_as(P), 1, None) == 1  # row ny-1
+    L.hw_plan_destroy(h)

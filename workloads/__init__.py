@@ -24,6 +24,16 @@ smooth random medium below stands in for it):
   shots     64 independent layered 2D shots, sides U{256..2048}, step counts
             U{500..5000}.
   requests  Poisson stream of mixed 2D layered / 3D smooth requests.
+  paper_elastic2d
+            the elastic experiment of App. A: 2D, 600 x 600 cells of 1/125
+            km, dt = 1e-4 s, 60000 steps, periodic in x, free surfaces at the
+            top and bottom rows, at rest; a 5 Hz Ricker source on vy ten
+            cells below the top surface at x = 200, a receiver at x = 400 at
+            the same depth.  The paper's medium (a Marmousi2 subsection) is
+            not available; a layered medium with undulating interfaces
+            stands in for it, spanning the paper's stated extremes (minimum
+            shear speed 1.0117 km/s, maximum compressional speed 4.6992
+            km/s, density 2.0293 to 2.6230).
   paper2d   the acoustic experiment of Sec. 3: homogeneous rho = c = 1,
             600 x 600 cells of 1/125 m (ppw = 10; 1800 x 1800 of 1/375 m for
             ppw = 30), dt = 1e-4 s, 60000 steps, order 4, at rest; a point
@@ -169,6 +179,91 @@ class Elastic3D:
         names = ("vx", "vy", "vz", "sxx", "syy", "szz", "sxy", "sxz", "syz")
         z = np.zeros((self.nz, self.ny, self.nx))
         return {k: self.init.get(k, z) for k in names}
+
+
+@dataclass
+class Elastic2D:
+    """2D velocity-stress problem bounded in y by free surfaces (rows 0 and
+    ny-1); arrays [ny, nx]."""
+    nx: int
+    ny: int
+    dx: float
+    dt: float
+    rho: np.ndarray
+    lam: np.ndarray
+    mu: np.ndarray
+    init: dict               # field name -> [ny, nx] array (missing = 0)
+    nsteps: int = 0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+    source: tuple | None = None        # (ix, iy, samples): vy at (ix, iy+1/2)
+    receivers: list | None = None      # [(ix, iy), ...]
+    order: int = 2
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+    def fields(self):
+        z = np.zeros((self.ny, self.nx))
+        return {k: self.init.get(k, z) for k in ("vx", "vy", "sxx", "syy", "sxy")}
+
+
+# the extremes the paper states for its elastic medium (App. A), km/s and
+# Gt/km^3
+APP_A_CS_MIN = 1.0117
+APP_A_CP_MAX = 4.6992
+APP_A_RHO = (2.0293, 2.6230)
+
+
+def layered_elastic2d(nx, ny, seed, nlayers=5, vpvs=1.85, swing=0.05):
+    """rho, lambda, mu [ny, nx] of a layered medium whose interfaces
+    undulate periodically in x: the normalised depth s = (j + d(i)) / (ny-1)
+    (clipped to [0, 1]) with d a sum of two seeded periodic sines of
+    amplitude swing*ny and swing*ny/2; the P speed grows with s, 70% as a
+    gradient and 30% in nlayers equal steps, from APP_A_CS_MIN * vpvs to
+    APP_A_CP_MAX; the S speed is the P speed / vpvs; the density follows the
+    P speed linearly over APP_A_RHO.  Top and bottom rows reach the extremes
+    wherever the interfaces rise above the top or sink below the bottom."""
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=2)
+    x = 2.0 * math.pi * np.arange(nx) / nx
+    d = swing * ny * (np.sin(x + ph[0]) + 0.5 * np.sin(3.0 * x + ph[1]))
+    s = np.clip((np.arange(ny)[:, None] + d[None, :]) / (ny - 1), 0.0, 1.0)
+    shape = 0.7 * s + 0.3 * np.minimum(np.floor(nlayers * s), nlayers - 1) / (nlayers - 1)
+    cp_top = APP_A_CS_MIN * vpvs
+    cp = cp_top + (APP_A_CP_MAX - cp_top) * shape
+    cs = cp / vpvs
+    rho = APP_A_RHO[0] + (APP_A_RHO[1] - APP_A_RHO[0]) * (cp - cp_top) / (APP_A_CP_MAX - cp_top)
+    mu = rho * cs ** 2
+    lam = rho * (cp ** 2 - 2.0 * cs ** 2)
+    return rho, lam, mu
+
+
+def paper_elastic2d(nsteps=60000, f0=5.0, delay=None, amplitude=1.0,
+                    seed=None, n=600) -> Elastic2D:
+    """The elastic setup of App. A on the medium of layered_elastic2d.
+
+    n x n cells of dx = 1/125 km (ppw 10 at 12.5 Hz for the slowest shear
+    wave), dt = 1e-4 s.  The vy update of step m is centred at t_m = m dt,
+    so step m adds amplitude * dt / dx^2 * ricker(t_m - delay) (a point force
+    per unit mass spread over one cell), delayed by 1.2 / f0 and cut after
+    delay + 1.2 / f0.  Source on vy at (n/3, 10 + 1/2), receiver at cell
+    (2n/3, 10): ten cells below the free surface at row 0."""
+    dx = 1.0 / 125.0
+    dt = 1e-4
+    delay = 1.2 / f0 if delay is None else delay
+    t = np.arange(nsteps) * dt - delay
+    samples = amplitude * dt / (dx * dx) * ricker(t, f0)
+    keep = int(np.ceil((delay + 1.2 / f0) / dt)) + 1
+    samples = samples[:min(keep, nsteps)]
+    rho, lam, mu = layered_elastic2d(n, n, seed_for(7) if seed is None else seed)
+    return Elastic2D(n, n, dx, dt, rho, lam, mu, {}, nsteps=nsteps,
+                     name=f"elastic2d-{n}x{n}-free-surface-ricker",
+                     meta={"f0": f0, "delay": delay,
+                           "cp_max": float(np.sqrt((lam + 2 * mu) / rho).max())},
+                     source=(n // 3, 10, samples),
+                     receivers=[(2 * n // 3, 10)])
 
 
 def small2d(n=128, nsteps=1000, order=2, cfl=0.5, sigma=8.0) -> Acoustic2D:
