@@ -284,6 +284,17 @@ def read_paper_golden(path=PAPER_GOLDEN):
             "energy_steps": np.array(es), "energy": np.array(ev)}
 
 
+def trace_rel_l2(trace, gold, col):
+    """Relative l2 distance of a receiver record (one value per step) from
+    the reference's column col, over the reference rows the run reached;
+    None if the reference is still zero there."""
+    sel = gold["steps"] <= len(trace)
+    ref = gold["rec"][sel, col]
+    got = trace[gold["steps"][sel] - 1]
+    norm = np.linalg.norm(ref)
+    return float(np.linalg.norm(got - ref) / norm) if norm > 0 else None
+
+
 def run_paper(hw, torch, nsteps=60000):
     """The acoustic experiment of Sec. 3: 600^2 (ppw 10), dt 1e-4, 60000
     steps, Ricker point source on the pressure, one receiver; every storage
@@ -327,12 +338,11 @@ def run_paper(hw, torch, nsteps=60000):
         # for a conserving run)
         after = esteps >= src_end + every
         e_after = energy[after]
-        r["energy_change_after_source"] = float((e_after[-1] - e_after[0]) / e_after[0])
+        # null when the run ends before the source has stopped
+        r["energy_change_after_source"] = (
+            float((e_after[-1] - e_after[0]) / e_after[0]) if len(e_after) > 1 else None)
         if gold is not None:
-            idx = gold["steps"] - 1
-            p = rec[idx, 0]
-            ref = gold["rec"][:, 0]
-            r["p_trace_rel_l2_vs_fp64"] = float(np.linalg.norm(p - ref) / np.linalg.norm(ref))
+            r["p_trace_rel_l2_vs_fp64"] = trace_rel_l2(rec[:, 0], gold, 0)
             ge = np.interp(esteps, gold["energy_steps"], gold["energy"])
             m = esteps >= every
             r["energy_max_rel_dev_vs_fp64"] = float(np.max(np.abs(energy[m] - ge[m]) / ge[m]))
@@ -349,12 +359,129 @@ def run_paper(hw, torch, nsteps=60000):
     ms, rec30, _, _ = one(w30, "f32", "none")
     res["f32_ppw30_glups"] = w30.cells * nsteps / (ms * 1e-3) / 1e9
     if gold is not None:
-        idx = gold["steps"] - 1
-        ref = gold["rec"][:, 0]
-        res["discretisation_rel_l2_ppw10_vs_ppw30"] = float(
-            np.linalg.norm(rec30[idx, 0] - ref) / np.linalg.norm(ref))
+        res["discretisation_rel_l2_ppw10_vs_ppw30"] = trace_rel_l2(rec30[:, 0], gold, 0)
     print(f"# paper2d ppw30 f32: {res.get('discretisation_rel_l2_ppw10_vs_ppw30')}",
           file=sys.stderr, flush=True)
+    return res
+
+
+APP_A_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
+                            "golden", "elastic2d_app_a_fp64.csv")
+APP_A_VARIANTS = [("f32", "none"), ("f16", "none"), ("f16", "fast2sum"),
+                  ("f16", "twosum"), ("bf16", "none"), ("bf16", "twosum")]
+
+
+def read_app_a_golden(path=APP_A_GOLDEN):
+    """The FP64 oracle's receiver record (five fields every 50th step) and
+    energy (every 500th) of the App. A experiment, or None."""
+    if not os.path.exists(path):
+        return None
+    steps, rec, es, ev = [], [], [], []
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            f = line.strip().split(",")
+            if f[0] == "E":
+                es.append(int(f[1]))
+                ev.append(float(f[2]))
+            else:
+                steps.append(int(f[0]))
+                rec.append([float(x) for x in f[1:6]])
+    return {"steps": np.array(steps), "rec": np.array(rec),
+            "energy_steps": np.array(es), "energy": np.array(ev)}
+
+
+def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
+    """The elastic experiment of App. A: 600^2, free surfaces at the top and
+    bottom rows, periodic in x, dt 1e-4, 60000 steps, Ricker source on vy ten
+    cells below the surface, one receiver; every storage variant against the
+    FP64 oracle's vy record and energy.  Plus the two-pass kernels' rate on
+    a big^2 grid of the same medium type (HBM-resident, no source)."""
+    import workloads
+    gold = read_app_a_golden()
+    every = 500
+    w = workloads.paper_elastic2d(nsteps=nsteps)
+    samples = w.source[2]
+    src_end = len(samples)
+    out = {}
+    stream = torch.cuda.current_stream()
+    for storage, comp in APP_A_VARIANTS:
+        pb = hw.Problem("elastic2d", w.nx, w.ny, 1, 2, storage, comp, w.dx, w.dt, 0,
+                        nsteps // every + 2, src_cap=len(samples), rec_cap=1,
+                        rec_steps=nsteps)
+        plan = hw.Plan(pb)
+        plan.set_material([w.rho, w.lam, w.mu])
+        plan.set_fields(w.fields())
+        plan.set_source(*w.source)
+        plan.set_receivers(w.receivers)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        plan.advance(nsteps, every)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        rec = plan.receiver_trace()[:, 0, :]
+        energy, esteps = plan.energy_trace()
+        plan.close()
+        r = {"glups": w.cells * nsteps / (ms * 1e-3) / 1e9, "ms_total": ms}
+        after = esteps >= src_end + every
+        e_after = energy[after]
+        # null when the run ends before the source has stopped
+        r["energy_change_after_source"] = (
+            float((e_after[-1] - e_after[0]) / e_after[0]) if len(e_after) > 1 else None)
+        if gold is not None:
+            r["vy_trace_rel_l2_vs_fp64"] = trace_rel_l2(rec[:, 1], gold, 1)
+            ge = np.interp(esteps, gold["energy_steps"], gold["energy"])
+            m = esteps >= every
+            r["energy_max_rel_dev_vs_fp64"] = float(np.max(np.abs(energy[m] - ge[m]) / ge[m]))
+        out[f"{storage}+{comp}"] = r
+        print(f"# app_a {storage}+{comp}: {r}", file=sys.stderr, flush=True)
+    res = {"workload": f"elastic2d order-2 {w.nx}x{w.ny}, free surfaces on rows 0 and "
+                       f"{w.ny - 1}, periodic in x, dx 1/125 km, dt 1e-4 s, {nsteps} steps, "
+                       "layered stand-in medium (cs >= 1.0117, cp <= 4.6992 km/s), "
+                       "Ricker 5 Hz on vy at (200, 10.5), receiver at (400, 10) (App. A)",
+           "reference": "FP64 oracle" if gold is not None else None,
+           "variants": out}
+    # the two-pass kernels at an HBM-resident size: bytes per cell-step of
+    # the two passes: the velocity pass reads 3 stress words, 2 velocity
+    # words and b, writes 2 velocity words; the stress pass reads 2 velocity
+    # words, 3 stress words and 3 coefficients, writes 3 stress words -> 15
+    # words + 4 fp32 coefficients (a word is 4 bytes for fp32 or a 16-bit
+    # value with its compensation term, 2 for a plain 16-bit value); one
+    # fused pass would need 10 words + 4 coefficients
+    rho, lam, mu = workloads.layered_elastic2d(big, big, workloads.seed_for(7, 1))
+    cp = float(np.sqrt((lam + 2 * mu) / rho).max())
+    dt = 0.5 / cp
+    z = np.zeros((big, big))
+    f0 = {"sxx": workloads.gaussian2d(big, big, big // 2, big // 2, 8.0)}
+    thr = {}
+    for storage, comp in (("f32", "none"), ("f16", "twosum"), ("f16", "none")):
+        pb = hw.Problem("elastic2d", big, big, 1, 2, storage, comp, 1.0, dt, 0, 0)
+        plan = hw.Plan(pb)
+        plan.set_material([rho, lam, mu])
+        plan.set_fields({"vx": z, "vy": z, "sxx": f0["sxx"], "syy": z, "sxy": z})
+        plan.advance(20)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        plan.advance(big_steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / big_steps
+        plan.close()
+        word = 4 if (storage == "f32" or comp != "none") else 2
+        bpc = 15 * word + 4 * 4
+        thr[f"{storage}+{comp}"] = {
+            "glups": big * big / (ms * 1e-3) / 1e9, "ms_per_step": ms,
+            "bytes_per_cell_step_two_pass": bpc,
+            "hbm_gbs_two_pass": bpc * big * big / (ms * 1e-3) / 1e9}
+        print(f"# app_a {big}^2 {storage}+{comp}: {thr[f'{storage}+{comp}']}",
+              file=sys.stderr, flush=True)
+    res[f"throughput_{big}"] = thr
     return res
 
 
@@ -414,9 +541,10 @@ def main():
     ap.add_argument("--elastic-steps", type=int, default=2000)
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--sections", default="2d,3d,batched,serving,paper",
+    ap.add_argument("--sections", default="2d,3d,batched,serving,paper,app_a",
                     help="comma list of workloads to run: 2d (always reported), "
-                         "3d, batched, serving, paper (the Sec. 3 experiment)")
+                         "3d, batched, serving, paper (the Sec. 3 experiment), "
+                         "app_a (the elastic experiment of App. A)")
     ap.add_argument("--paper-steps", type=int, default=60000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy (calibrates "
@@ -490,6 +618,8 @@ def main():
         extra["serving"] = run_serving(hw, torch, args.requests, head["glups"], g3)
     if "paper" in sections:
         extra["paper2d"] = run_paper(hw, torch, args.paper_steps)
+    if "app_a" in sections:
+        extra["elastic2d_app_a"] = run_app_a(hw, torch, args.paper_steps)
     f32 = results.get("f32+none")
     out = {
         "metric": METRIC,
