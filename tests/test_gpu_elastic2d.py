@@ -276,3 +276,107 @@ def test_app_a_full_size_sampled():
         for k in F:
             assert after[k][j, i] == o[k][jc, m], (k, j, i)
             assert cafter[k][j, i] == oc[k][jc, m], (k, j, i)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 3), (5, 3), (64, 4), (65, 5), (3, 130), (129, 9)])
+def test_degenerate_and_ragged_grids(nx, ny):
+    """The smallest body (one interior row), one column (x wraps onto
+    itself), exact and ragged tiles, a tall thin strip: bit-exact against
+    the oracle with the source and a receiver."""
+    rho, lam, mu = workloads.layered_elastic2d(nx, ny, 750 + nx, swing=0.2)
+    cp = np.sqrt((lam + 2 * mu) / rho).max()
+    dt = 0.5 / cp
+    rng = np.random.default_rng(751)
+    f = {k: oracle.round_to(0.05 * rng.normal(size=(ny, nx)), "f16") for k in F}
+    f["syy"][0] = f["syy"][-1] = 0.0
+    f["vy"][-1] = f["sxy"][-1] = 0.0
+    src = (nx // 2, ny // 2 - 1 if ny > 3 else 0)
+    samples = _samples(12, dt)
+    rec = [(nx - 1, ny - 1), (0, 0)]
+    pb = hw.Problem("elastic2d", nx, ny, 1, 2, "f16", "twosum", 1.0, dt, 0, 0,
+                    src_cap=12, rec_cap=2, rec_steps=20)
+    plan = hw.Plan(pb)
+    plan.set_material([rho, lam, mu])
+    plan.set_fields(f)
+    plan.set_source(src[0], src[1], samples)
+    plan.set_receivers(rec)
+    plan.advance(20)
+    got, gc = plan.get_fields(comps=True)
+    tr = plan.receiver_trace()
+    plan.close()
+    w, wc, _, wt = oracle.elastic2d(nx, ny, 1.0, dt, rho, lam, mu, f, storage="f16",
+                                    stencil="f32", comp="twosum", nsteps=20,
+                                    source=(src[0], src[1], samples), receivers=rec)
+    assert_bitexact(got, w, f"{nx}x{ny}")
+    assert_bitexact(gc, wc, f"{nx}x{ny} comps")
+    assert np.array_equal(tr, wt)
+
+
+def test_power_of_two_field_scale_is_exact():
+    """Fields held times 2^4 (the range scaling of Sec. 5): the unscaled
+    results, receiver records included, equal the unscaled run bit for bit
+    (source samples are given already scaled).  bf16, whose exponent range
+    keeps every value of this run normal (in fp16 the compensation terms are
+    often subnormal, where a power-of-two scale changes the rounding)."""
+    rho, lam, mu, cp = _medium(761)
+    dt = 0.5 / cp
+    f = _fields(762, "bf16", scale=0.5)
+    samples = _samples(20, dt)
+    out = []
+    for k in (0, 4):
+        pb = hw.Problem("elastic2d", NX, NY, 1, 2, "bf16", "twosum", 1.0, dt, k, 0,
+                        src_cap=20, rec_cap=len(RECS), rec_steps=30)
+        plan = hw.Plan(pb)
+        plan.set_material([rho, lam, mu])
+        plan.set_fields(f)
+        plan.set_source(SRC[0], SRC[1], samples * 2.0 ** k)
+        plan.set_receivers(RECS)
+        plan.advance(30)
+        out.append((plan.get_fields(comps=True), plan.receiver_trace()))
+        plan.close()
+    (a, ca), ta = out[0]
+    (b, cb), tb = out[1]
+    assert_bitexact(b, a, "scaled")
+    assert_bitexact(cb, ca, "scaled comps")
+    assert np.array_equal(tb, ta)
+
+
+def test_batch_beyond_the_launch_limit():
+    """70 small elastic plans of uneven size and step count in one batch (one
+    launch pair per plan, counters ticked in groups of 64): each equals its
+    solo run."""
+    plans, steps, made = [], [], []
+    for i in range(70):
+        nx, ny = 20 + i % 9, 3 + i % 6
+        rho, lam, mu = workloads.layered_elastic2d(nx, ny, 800 + i, swing=0.2)
+        dt = 0.5 / np.sqrt((lam + 2 * mu) / rho).max()
+        rng = np.random.default_rng(900 + i)
+        f = {k: oracle.round_to(0.05 * rng.normal(size=(ny, nx)), "f16") for k in F}
+        f["syy"][0] = f["syy"][-1] = 0.0
+        f["vy"][-1] = f["sxy"][-1] = 0.0
+        pb = hw.Problem("elastic2d", nx, ny, 1, 2, "f16", "twosum", 1.0, dt, 0, 0,
+                        src_cap=5, rec_cap=1, rec_steps=12)
+        p = hw.Plan(pb)
+        p.set_material([rho, lam, mu])
+        p.set_fields(f)
+        if i % 2:
+            p.set_source(0, 0, [0.25, -0.5, 0.125, 0.0, 1.0])
+            p.set_receivers([(nx - 1, ny - 1)])
+        plans.append(p)
+        steps.append(3 + i % 9)
+        made.append((pb, [rho, lam, mu], f, i % 2))
+    hw.batch_advance(plans, steps)
+    for p, n, (pb, mat, f, forced) in zip(plans, steps, made):
+        q = hw.Plan(pb)
+        q.set_material(mat)
+        q.set_fields(f)
+        if forced:
+            q.set_source(0, 0, [0.25, -0.5, 0.125, 0.0, 1.0])
+            q.set_receivers([(pb.nx - 1, pb.ny - 1)])
+        q.advance(n)
+        assert_bitexact(p.get_fields(), q.get_fields(), "batched")
+        if forced:
+            assert np.array_equal(p.receiver_trace(), q.receiver_trace())
+        q.close()
+    for p in plans:
+        p.close()
