@@ -399,9 +399,11 @@ def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
     FP64 oracle's vy record and energy.  Plus the two-pass kernels' rate on
     a big^2 grid of the same medium type (HBM-resident, no source)."""
     import workloads
+    from paper_2310_00236_amd import tuning
     gold = read_app_a_golden()
     every = 500
     w = workloads.paper_elastic2d(nsteps=nsteps)
+    shapes = hw.tiles("elastic2d")
     samples = w.source[2]
     src_end = len(samples)
     out = {}
@@ -411,6 +413,8 @@ def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
                         nsteps // every + 2, src_cap=len(samples), rec_cap=1,
                         rec_steps=nsteps)
         plan = hw.Plan(pb)
+        tile = tuning.best_tile("elastic2d", 2, storage, comp, w.nx, w.ny)
+        plan.set_tile(tile)
         plan.set_material([w.rho, w.lam, w.mu])
         plan.set_fields(w.fields())
         plan.set_source(*w.source)
@@ -426,7 +430,8 @@ def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
         rec = plan.receiver_trace()[:, 0, :]
         energy, esteps = plan.energy_trace()
         plan.close()
-        r = {"glups": w.cells * nsteps / (ms * 1e-3) / 1e9, "ms_total": ms}
+        r = {"glups": w.cells * nsteps / (ms * 1e-3) / 1e9, "ms_total": ms,
+             "tile": hw.tile_label(shapes[tile])}
         after = esteps >= src_end + every
         e_after = energy[after]
         # null when the run ends before the source has stopped
@@ -461,6 +466,8 @@ def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
     for storage, comp in (("f32", "none"), ("f16", "twosum"), ("f16", "none")):
         pb = hw.Problem("elastic2d", big, big, 1, 2, storage, comp, 1.0, dt, 0, 0)
         plan = hw.Plan(pb)
+        tile = tuning.best_tile("elastic2d", 2, storage, comp, big, big)
+        plan.set_tile(tile)
         plan.set_material([rho, lam, mu])
         plan.set_fields({"vx": z, "vy": z, "sxx": f0["sxx"], "syy": z, "sxy": z})
         plan.advance(20)
@@ -477,6 +484,7 @@ def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
         bpc = 15 * word + 4 * 4
         thr[f"{storage}+{comp}"] = {
             "glups": big * big / (ms * 1e-3) / 1e9, "ms_per_step": ms,
+            "tile": hw.tile_label(shapes[tile]),
             "bytes_per_cell_step_two_pass": bpc,
             "hbm_gbs_two_pass": bpc * big * big / (ms * 1e-3) / 1e9}
         print(f"# app_a {big}^2 {storage}+{comp}: {thr[f'{storage}+{comp}']}",

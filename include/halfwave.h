@@ -277,8 +277,10 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  *   elastic3d   0 = two passes per step (velocities, then stresses), one
  *               plane per workgroup; 2 = one fused pass per step, a
  *               workgroup walks a tx by ty column through tz planes;
- *   elastic2d   0 = two passes per step (velocities, then stresses), one
- *               tx by ty tile per workgroup.
+ *   elastic2d   1 = one fused pass per step (each thread recomputes the
+ *               neighbouring new velocities its stresses read), 0 = two
+ *               passes (velocities, then stresses); one tx by ty tile per
+ *               workgroup.
  * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
  * results.  Any of the output pointers may be NULL. */
 int32_t hw_tile_count(int32_t physics);

@@ -2,10 +2,12 @@
 // Eq. (A1) of App. A, 2nd-order staggered differences, periodic in x, free
 // surfaces on the normal-stress rows 0 and ny-1.
 //
-// A step is two passes over 64 x 4 tiles, one thread per cell: the velocity
-// pass reads the old stresses and velocities (field set par) and writes the
-// new velocities (set par^1); the stress pass reads the new velocities and
-// the old stresses and writes the new stresses (set par^1).  At the
+// Two kernel shapes, one thread per cell of 64 x 4 tiles: the fused shape
+// computes a step in one pass (each thread recomputes the four neighbouring
+// new velocities its stresses read); the two-pass shape runs a velocity
+// pass (old stresses and velocities of field set par -> new velocities in
+// set par^1) and then a stress pass (new velocities and old stresses -> new
+// stresses in set par^1).  At the
 // surfaces sxy is odd (the value half a cell outside is minus the value half
 // a cell inside), syy stays zero, and sxx moves with the plate modulus
 // carried by the per-cell coefficient tables.  Rows that lie outside the
@@ -48,92 +50,106 @@ __device__ __forceinline__ int wrapx(int i, int n)
 
 }  // namespace
 
-// New velocities of one cell.  FRC: the plan has a point source (on vy) or
-// receivers; the source sample of this step joins the vy increment after
-// the multiplication by the staggered buoyancy.
+// The new velocity words of one cell (from the old stresses and velocities
+// of set par): vx at (i+1/2, j), and vy at (i, j+1/2) -- on row ny-1, which
+// lies outside the body, the old word.  FRC: the plan has a point source
+// (on vy) or receivers; the source sample of this step joins the vy
+// increment after the multiplication by the staggered buoyancy.  Shared by
+// the two-pass velocity kernel and the fused kernel, which recomputes its
+// neighbours' new velocities with them.
+template <class S, int COMP>
+__device__ __forceinline__ typename Word<S, COMP>::type new_vx(const El2dDesc &d, int par,
+                                                                int i, int j)
+{
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
+    using GW = const W HW_GLOBAL *;
+    const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
+    const int ip = wrapx(i + 1, nx);
+    const int row = j * pitch, q = row + i;
+    // the row below, clamped so that the load address lies in the grid
+    const int qdn = j > 0 ? q - pitch : q;
+    const float HW_GLOBAL *__restrict__ B = gmem(d.b);
+    GW sxx = gmem((const W *)d.f[par][2]);
+    GW sxy = gmem((const W *)d.f[par][4]);
+    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
+    // sxy below and above the point, imaged across the surfaces
+    const float s_dn = L(sxy, qdn), s_q = L(sxy, q);
+    const float lo = j == 0 ? -s_q : s_dn;
+    const float hi = j == ny - 1 ? -s_dn : s_q;
+    const float d1 = L(sxx, row + ip) - L(sxx, q);
+    const float d2 = hi - lo;
+    const float g = d.w * (d1 + d2);
+    const float bb = 0.5f * (B[q] + B[row + ip]);
+    const W old = gmem((const W *)d.f[par][0])[q];
+    auto v = WD::v(old), cc = WD::c(old);
+    update_store<S, COMP>(v, cc, bb * g);
+    return WD::make(v, cc);
+}
+
+template <class S, int COMP, bool FRC>
+__device__ __forceinline__ typename Word<S, COMP>::type new_vy(const El2dDesc &d, int par,
+                                                                int i, int j)
+{
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
+    using GW = const W HW_GLOBAL *;
+    const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
+    const int im = wrapx(i - 1, nx);
+    const int row = j * pitch, q = row + i;
+    const W old = gmem((const W *)d.f[par][1])[q];
+    if (j >= ny - 1)
+        return old;
+    const float HW_GLOBAL *__restrict__ B = gmem(d.b);
+    GW syy = gmem((const W *)d.f[par][3]);
+    GW sxy = gmem((const W *)d.f[par][4]);
+    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
+    const float d1 = L(sxy, q) - L(sxy, row + im);
+    const float d2 = L(syy, q + pitch) - L(syy, q);
+    const float g = d.w * (d1 + d2);
+    const float bb = 0.5f * (B[q] + B[q + pitch]);
+    float inc = bb * g;
+    if constexpr (FRC) {
+        if (d.src_n > 0 && i == d.src_x && j == d.src_y) {
+            const int64_t n = *gmem(d.step);
+            if (n < d.src_n)
+                inc = inc + gmem(d.src)[n];
+        }
+    }
+    auto v = WD::v(old), cc = WD::c(old);
+    update_store<S, COMP>(v, cc, inc);
+    return WD::make(v, cc);
+}
+
+// Two-pass step, first pass: the new velocities of one cell to set par^1.
 template <class S, int COMP, bool FRC>
 __global__ __launch_bounds__(kThreads) void el2d_velocity_kernel(const El2dDesc d,
                                                                  int par)
 {
-    using WD = Word<S, COMP>;
-    using W = typename WD::type;
-    using GW = const W HW_GLOBAL *;
+    using W = typename Word<S, COMP>::type;
     const Where c = where(d);
     if (!c.valid)
         return;
-    const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
-    const int i = c.i, j = c.j;
-    const int ip = wrapx(i + 1, nx), im = wrapx(i - 1, nx);
-    const int row = j * pitch, q = row + i;
-    // neighbour rows, clamped so that every load address lies in the grid
-    // whichever branch uses it
-    const int qdn = j > 0 ? q - pitch : q, qup = j < ny - 1 ? q + pitch : q;
-    const float w = d.w;
-    const float HW_GLOBAL *__restrict__ B = gmem(d.b);
-    GW sxx = gmem((const W *)d.f[par][2]);
-    GW syy = gmem((const W *)d.f[par][3]);
-    GW sxy = gmem((const W *)d.f[par][4]);
-    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
-    const float bq = B[q];
-    {   // vx at (i+1/2, j); sxy below and above, imaged across the surfaces
-        const float s_dn = L(sxy, qdn), s_q = L(sxy, q);
-        const float lo = j == 0 ? -s_q : s_dn;
-        const float hi = j == ny - 1 ? -s_dn : s_q;
-        const float d1 = L(sxx, row + ip) - L(sxx, q);
-        const float d2 = hi - lo;
-        const float g = w * (d1 + d2);
-        const float bb = 0.5f * (bq + B[row + ip]);
-        const W old = gmem((const W *)d.f[par][0])[q];
-        auto v = WD::v(old), cc = WD::c(old);
-        update_store<S, COMP>(v, cc, bb * g);
-        gmem((W *)d.f[par ^ 1][0])[q] = WD::make(v, cc);
-    }
-    const W oldy = gmem((const W *)d.f[par][1])[q];
-    if (j < ny - 1) {   // vy at (i, j+1/2)
-        const float d1 = L(sxy, q) - L(sxy, row + im);
-        const float d2 = L(syy, qup) - L(syy, q);
-        const float g = w * (d1 + d2);
-        const float bb = 0.5f * (bq + B[qup]);
-        float inc = bb * g;
-        if constexpr (FRC) {
-            if (d.src_n > 0 && i == d.src_x && j == d.src_y) {
-                const int64_t n = *gmem(d.step);
-                if (n < d.src_n)
-                    inc = inc + gmem(d.src)[n];
-            }
-        }
-        auto v = WD::v(oldy), cc = WD::c(oldy);
-        update_store<S, COMP>(v, cc, inc);
-        gmem((W *)d.f[par ^ 1][1])[q] = WD::make(v, cc);
-    } else {
-        gmem((W *)d.f[par ^ 1][1])[q] = oldy;
-    }
+    const int q = c.j * (int)d.pitch + c.i;
+    gmem((W *)d.f[par ^ 1][0])[q] = new_vx<S, COMP>(d, par, c.i, c.j);
+    gmem((W *)d.f[par ^ 1][1])[q] = new_vy<S, COMP, FRC>(d, par, c.i, c.j);
 }
 
-// New stresses of one cell from the new velocities (set par^1).
+// The new stresses of cell (i, j) from the new velocities it needs (vx at
+// (i, j), (i-1, j), (i, j+1); vy at (i, j), (i, j-1), (i+1, j)) given as
+// values, old stresses from set par, written to set par^1.
 template <class S, int COMP>
-__global__ __launch_bounds__(kThreads) void el2d_stress_kernel(const El2dDesc d,
-                                                               int par)
+__device__ __forceinline__ void stress_update(const El2dDesc &d, int par, int i, int j,
+                                              float vx_q, float vx_im, float vx_jp,
+                                              float vy_q, float vy_dn, float vy_ip)
 {
     using WD = Word<S, COMP>;
     using W = typename WD::type;
-    using GW = const W HW_GLOBAL *;
-    const Where c = where(d);
-    if (!c.valid)
-        return;
-    const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
-    const int i = c.i, j = c.j;
-    const int ip = wrapx(i + 1, nx), im = wrapx(i - 1, nx);
-    const int row = j * pitch, q = row + i;
+    const int ny = (int)d.ny;
+    const int q = j * (int)d.pitch + i;
     const float w = d.w;
     const bool surface = j == 0 || j == ny - 1;
-    const int qdn = j > 0 ? q - pitch : q, qup = j < ny - 1 ? q + pitch : q;
-    GW vx = gmem((const W *)d.f[par ^ 1][0]);
-    GW vy = gmem((const W *)d.f[par ^ 1][1]);
-    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
-    const float vx_q = L(vx, q), vy_q = L(vy, q);
-    const float ex = w * (vx_q - L(vx, row + im));
-    const float vy_dn = L(vy, qdn);
+    const float ex = w * (vx_q - vx_im);
     const float ey = surface ? 0.0f : w * (vy_q - vy_dn);
     const float l2m = gmem(d.l2m)[q], lam = gmem(d.lam)[q];
     auto upd = [&](int f, float inc) {
@@ -151,13 +167,74 @@ __global__ __launch_bounds__(kThreads) void el2d_stress_kernel(const El2dDesc d,
     else
         keep(3);
     if (j < ny - 1) {   // sxy at (i+1/2, j+1/2)
-        const float a1 = L(vy, row + ip) - vy_q;
-        const float a2 = L(vx, qup) - vx_q;
+        const float a1 = vy_ip - vy_q;
+        const float a2 = vx_jp - vx_q;
         const float g = w * (a1 + a2);
         upd(4, gmem(d.mxy)[q] * g);
     } else {
         keep(4);
     }
+}
+
+// One-pass step: each thread computes its cell's new velocities (stored)
+// and the four neighbouring new velocities its stresses read, recomputed
+// from old values with the same operations, so new velocities never pass
+// through memory within a step; then its new stresses.  Every word of the
+// state is read from set par and written to set par^1 once per step (the
+// neighbours' old words are re-read from the caches).
+template <class S, int COMP, bool FRC>
+__global__ __launch_bounds__(kThreads) void el2d_fused_kernel(const El2dDesc d, int par)
+{
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
+    const Where c = where(d);
+    if (!c.valid)
+        return;
+    const int nx = (int)d.nx, ny = (int)d.ny;
+    const int i = c.i, j = c.j;
+    const int q = j * (int)d.pitch + i;
+    const W wx = new_vx<S, COMP>(d, par, i, j);
+    const W wy = new_vy<S, COMP, FRC>(d, par, i, j);
+    gmem((W *)d.f[par ^ 1][0])[q] = wx;
+    gmem((W *)d.f[par ^ 1][1])[q] = wy;
+    auto V = [](W x) { return S::load(WD::v(x)); };
+    const float vx_q = V(wx), vy_q = V(wy);
+    const float vx_im = V(new_vx<S, COMP>(d, par, wrapx(i - 1, nx), j));
+    // the rows above and below are read only off the surfaces (ey) and
+    // above the last row (sxy); rows stay uniform across a wavefront
+    float vy_dn = 0.0f, vx_jp = 0.0f, vy_ip = 0.0f;
+    if (j > 0 && j < ny - 1)
+        vy_dn = V(new_vy<S, COMP, FRC>(d, par, i, j - 1));
+    if (j < ny - 1) {
+        vx_jp = V(new_vx<S, COMP>(d, par, i, j + 1));
+        vy_ip = V(new_vy<S, COMP, FRC>(d, par, wrapx(i + 1, nx), j));
+    }
+    stress_update<S, COMP>(d, par, i, j, vx_q, vx_im, vx_jp, vy_q, vy_dn, vy_ip);
+}
+
+// Two-pass step, second pass: the new stresses of one cell from the new
+// velocities in set par^1.
+template <class S, int COMP>
+__global__ __launch_bounds__(kThreads) void el2d_stress_kernel(const El2dDesc d,
+                                                               int par)
+{
+    using WD = Word<S, COMP>;
+    using W = typename WD::type;
+    using GW = const W HW_GLOBAL *;
+    const Where c = where(d);
+    if (!c.valid)
+        return;
+    const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
+    const int i = c.i, j = c.j;
+    const int ip = wrapx(i + 1, nx), im = wrapx(i - 1, nx);
+    const int row = j * pitch, q = row + i;
+    // neighbour rows, clamped so that every load address lies in the grid
+    const int qdn = j > 0 ? q - pitch : q, qup = j < ny - 1 ? q + pitch : q;
+    GW vx = gmem((const W *)d.f[par ^ 1][0]);
+    GW vy = gmem((const W *)d.f[par ^ 1][1]);
+    auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
+    stress_update<S, COMP>(d, par, i, j, L(vx, q), L(vx, row + im), L(vx, qup),
+                           L(vy, q), L(vy, qdn), L(vy, row + ip));
 }
 
 // Receivers after the step: the five new fields at each receiver cell, as
@@ -248,17 +325,27 @@ __global__ __launch_bounds__(kThreads) void el2d_energy_kernel(
 // ------------------------------------------------------------- dispatch --
 
 template <class S, int COMP>
-static hipError_t el2d_launch(const El2dDesc &d, int parity, bool forced, hipStream_t s)
+static hipError_t el2d_launch(const El2dDesc &d, int parity, bool forced, int tile,
+                              hipStream_t s)
 {
     const int64_t tiles = ((d.nx + kTx - 1) / kTx) * ((d.ny + kTy - 1) / kTy);
     const dim3 grid((unsigned)tiles), block(kThreads);
-    if (forced)
-        hipLaunchKernelGGL((el2d_velocity_kernel<S, COMP, true>), grid, block, 0, s, d,
-                           parity);
-    else
-        hipLaunchKernelGGL((el2d_velocity_kernel<S, COMP, false>), grid, block, 0, s, d,
-                           parity);
-    hipLaunchKernelGGL((el2d_stress_kernel<S, COMP>), grid, block, 0, s, d, parity);
+    if (kTilesEl2D[tile].kind == 1) {
+        if (forced)
+            hipLaunchKernelGGL((el2d_fused_kernel<S, COMP, true>), grid, block, 0, s, d,
+                               parity);
+        else
+            hipLaunchKernelGGL((el2d_fused_kernel<S, COMP, false>), grid, block, 0, s, d,
+                               parity);
+    } else {
+        if (forced)
+            hipLaunchKernelGGL((el2d_velocity_kernel<S, COMP, true>), grid, block, 0, s, d,
+                               parity);
+        else
+            hipLaunchKernelGGL((el2d_velocity_kernel<S, COMP, false>), grid, block, 0, s, d,
+                               parity);
+        hipLaunchKernelGGL((el2d_stress_kernel<S, COMP>), grid, block, 0, s, d, parity);
+    }
     if (forced && d.rec_n > 0)
         hipLaunchKernelGGL((el2d_record_kernel<S, COMP>), dim3(1), dim3(64), 0, s, d,
                            parity ^ 1);
@@ -267,25 +354,27 @@ static hipError_t el2d_launch(const El2dDesc &d, int parity, bool forced, hipStr
 
 template <class S>
 static hipError_t el2d_comp(const El2dDesc &d, int parity, int comp, bool forced,
-                            hipStream_t s)
+                            int tile, hipStream_t s)
 {
     switch (comp) {
-    case COMP_NONE: return el2d_launch<S, COMP_NONE>(d, parity, forced, s);
-    case COMP_FAST2SUM: return el2d_launch<S, COMP_FAST2SUM>(d, parity, forced, s);
-    case COMP_TWOSUM: return el2d_launch<S, COMP_TWOSUM>(d, parity, forced, s);
+    case COMP_NONE: return el2d_launch<S, COMP_NONE>(d, parity, forced, tile, s);
+    case COMP_FAST2SUM: return el2d_launch<S, COMP_FAST2SUM>(d, parity, forced, tile, s);
+    case COMP_TWOSUM: return el2d_launch<S, COMP_TWOSUM>(d, parity, forced, tile, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_el2d_step(const El2dDesc &d, int parity, int storage, int comp,
-                            bool forced, hipStream_t s)
+                            bool forced, int tile, hipStream_t s)
 {
     if (d.nx <= 0 || d.ny <= 0)
         return hipSuccess;
+    if (tile < 0 || tile >= kNumTilesEl2D)
+        return hipErrorInvalidValue;
     switch (storage) {
-    case HW_F32: return el2d_comp<F32>(d, parity, comp, forced, s);
-    case HW_F16: return el2d_comp<F16>(d, parity, comp, forced, s);
-    case HW_BF16: return el2d_comp<BF16>(d, parity, comp, forced, s);
+    case HW_F32: return el2d_comp<F32>(d, parity, comp, forced, tile, s);
+    case HW_F16: return el2d_comp<F16>(d, parity, comp, forced, tile, s);
+    case HW_BF16: return el2d_comp<BF16>(d, parity, comp, forced, tile, s);
     }
     return hipErrorInvalidValue;
 }

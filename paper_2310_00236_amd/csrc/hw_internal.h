@@ -118,9 +118,9 @@ constexpr TileShape kTiles2D[] = {{64, 16, 0, 1}, {64, 32, 0, 1}, {128, 16, 0, 1
 constexpr TileShape kTiles3D[] = {{64, 4, 0, 1},    {256, 1, 0, 1},   {64, 6, 2, 128},
                                   {64, 6, 2, 64},   {64, 6, 2, 512},  {64, 10, 2, 128},
                                   {64, 14, 2, 128}};
-// 2D elastic: two passes (velocities, then stresses), one 64 x 4 tile per
-// workgroup
-constexpr TileShape kTilesEl2D[] = {{64, 4, 0, 1}};
+// 2D elastic: one 64 x 4 tile per workgroup, kind 1 = one fused pass,
+// kind 0 = two passes (velocities, then stresses)
+constexpr TileShape kTilesEl2D[] = {{64, 4, 1, 1}, {64, 4, 0, 1}};
 constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
 constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
 constexpr int kNumTilesEl2D = sizeof(kTilesEl2D) / sizeof(kTilesEl2D[0]);
@@ -148,9 +148,10 @@ hipError_t launch_el3d_energy(const El3dDesc *d_desc, int parity, int64_t rows,
                               int storage, int stride, double *partial,
                               hipStream_t s);
 // One step of one 2D elastic plan (descriptor by value, field set parity
-// current); forced: the plan has a point source or receivers.
+// current, tile an index of kTilesEl2D); forced: the plan has a point source
+// or receivers.
 hipError_t launch_el2d_step(const El2dDesc &d, int parity, int storage, int comp,
-                            bool forced, hipStream_t s);
+                            bool forced, int tile, hipStream_t s);
 hipError_t launch_el2d_energy(const El2dDesc *d_desc, int parity, int64_t ny,
                               int storage, int stride, double *partial,
                               hipStream_t s);

@@ -298,7 +298,7 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
         for (int i = 0; i < n; ++i) {
             hw_plan *p = plans[i];
             hipError_t e = launch_el2d_step(p->he, parity[i], p->pb.storage, p->pb.comp,
-                                            p->counts(), s);
+                                            p->counts(), tile, s);
             if (e == hipSuccess && p->counts()) {
                 c.c[c.n++] = p->counter;
                 if (c.n == kMaxBatch) {

@@ -228,7 +228,7 @@ def test_elastic2d_problem_rules():
     assert L.hw_num_fields(2) == 5 and L.hw_num_materials(2) == 3
     assert hw.cfl_bound("elastic2d", 2) == pytest.approx(2 ** -0.5)
     assert L.hw_cfl_bound(2, 4) < 0
-    assert hw.tiles("elastic2d") == [(64, 4, 1, 0)]
+    assert hw.tiles("elastic2d") == [(64, 4, 1, 1), (64, 4, 1, 0)]
     e2 = dict(physics="elastic2d", order=2)
     for kw in (dict(order=4), dict(nz=2), dict(ny=2), dict(stencil="f64"),
                dict(stencil="storage"), dict(comp="twosum8")):

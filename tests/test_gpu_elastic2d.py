@@ -46,11 +46,12 @@ def _problem(storage, comp, dt, nsrc=0, nrec=0, rec_steps=0, trace_cap=0):
 
 
 def _gpu(storage, comp, rho, lam, mu, dt, f, nsteps, samples=None, recs=None,
-         energy_every=0):
+         energy_every=0, tile=0):
     ntrace = (nsteps // energy_every + 2) if energy_every else 0
     nsrc = 0 if samples is None else len(samples)
     nrec = 0 if recs is None else len(recs)
     plan = hw.Plan(_problem(storage, comp, dt, nsrc, nrec, nsteps, ntrace))
+    plan.set_tile(tile)
     plan.set_material([rho, lam, mu])
     plan.set_fields(f)
     if samples is not None:
@@ -74,17 +75,20 @@ def _oracle(storage, comp, rho, lam, mu, dt, f, nsteps, samples=None, recs=None,
                             receivers=recs)
 
 
+@pytest.mark.parametrize("tile", [0, 1])
 @pytest.mark.parametrize("storage,comp", [
     ("f32", "none"), ("f16", "none"), ("f16", "twosum"), ("f16", "fast2sum"),
     ("bf16", "none"), ("bf16", "twosum"), ("f32", "twosum")])
-def test_bitexact_with_source_and_receivers(storage, comp):
+def test_bitexact_with_source_and_receivers(storage, comp, tile):
     """45 steps in chunks of 15 between energy logs, the source active for
-    the first 30."""
+    the first 30; both kernel shapes (tile 0: one fused pass, tile 1: two
+    passes)."""
     rho, lam, mu, cp = _medium(701)
     dt = 0.5 / cp
     f = _fields(702, storage)
     samples = _samples(30, dt)
-    g, gc, gt, ge = _gpu(storage, comp, rho, lam, mu, dt, f, 45, samples, RECS, 15)
+    g, gc, gt, ge = _gpu(storage, comp, rho, lam, mu, dt, f, 45, samples, RECS, 15,
+                         tile)
     w, wc, we, wt = _oracle(storage, comp, rho, lam, mu, dt, f, 45, samples, RECS, 15)
     assert_bitexact(g, w, "fields")
     if comp != "none":
@@ -278,8 +282,9 @@ def test_app_a_full_size_sampled():
             assert cafter[k][j, i] == oc[k][jc, m], (k, j, i)
 
 
+@pytest.mark.parametrize("tile", [0, 1])
 @pytest.mark.parametrize("nx,ny", [(1, 3), (5, 3), (64, 4), (65, 5), (3, 130), (129, 9)])
-def test_degenerate_and_ragged_grids(nx, ny):
+def test_degenerate_and_ragged_grids(nx, ny, tile):
     """The smallest body (one interior row), one column (x wraps onto
     itself), exact and ragged tiles, a tall thin strip: bit-exact against
     the oracle with the source and a receiver."""
@@ -296,6 +301,7 @@ def test_degenerate_and_ragged_grids(nx, ny):
     pb = hw.Problem("elastic2d", nx, ny, 1, 2, "f16", "twosum", 1.0, dt, 0, 0,
                     src_cap=12, rec_cap=2, rec_steps=20)
     plan = hw.Plan(pb)
+    plan.set_tile(tile)
     plan.set_material([rho, lam, mu])
     plan.set_fields(f)
     plan.set_source(src[0], src[1], samples)
