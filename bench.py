@@ -575,7 +575,7 @@ def main():
                           "read_plus_write_gbs": 2 * a.numel() * 4 / ms / 1e6}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

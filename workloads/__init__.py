@@ -288,8 +288,8 @@ def paper2d(ppw=10, nsteps=60000, order=4, f0=5.0, delay=None,
     source on the pressure, one receiver).
 
     The grid has 600 * ppw / 10 cells per side with dx = (1/125) * 10 / ppw
-    (the baseline's 12.5 Hz maximal frequency at ppw points per wavelength
-    of c = 1 m/s) and dt = 1e-4 s.  Per-step source samples: the scheme's
+    (ppw points per wavelength of c = 1 at 12.5 Hz, 2.5 times the wavelet's
+    peak frequency) and dt = 1e-4 s.  Per-step source samples: the scheme's
     right-hand sides already carry dt (the stencil weights are c_k dt/dx)
     and a point source spreads over one cell of area dx*dx, so step n adds
     amplitude * dt / dx^2 * ricker(t_{n+1/2} - delay) with t_{n+1/2} =
