@@ -48,6 +48,18 @@ __device__ __forceinline__ int wrapx(int i, int n)
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
+// Load of a word that this pass reads once: non-temporal in the two-pass
+// kernels (at 4096^2 the passes run 12-21% faster), through the caches in
+// the one-pass kernel, whose threads re-read their neighbours' words.
+template <bool NT, class T>
+__device__ __forceinline__ T once(const T *base, int q)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(gmem(base) + q);
+    else
+        return gmem(base)[q];
+}
+
 // Store of one field word to the new set: non-temporal for words of 4 bytes
 // and more (a value with its compensation term, or fp32), plain for 2-byte
 // words -- the choice that measured fastest for the 2D acoustic step.
@@ -69,7 +81,7 @@ __device__ __forceinline__ void put(W *base, int q, W v)
 // increment after the multiplication by the staggered buoyancy.  Shared by
 // the two-pass velocity kernel and the fused kernel, which recomputes its
 // neighbours' new velocities with them.
-template <class S, int COMP>
+template <class S, int COMP, bool NT>
 __device__ __forceinline__ typename Word<S, COMP>::type new_vx(const El2dDesc &d, int par,
                                                                 int i, int j)
 {
@@ -93,13 +105,13 @@ __device__ __forceinline__ typename Word<S, COMP>::type new_vx(const El2dDesc &d
     const float d2 = hi - lo;
     const float g = d.w * (d1 + d2);
     const float bb = 0.5f * (B[q] + B[row + ip]);
-    const W old = gmem((const W *)d.f[par][0])[q];
+    const W old = once<NT>((const W *)d.f[par][0], q);
     auto v = WD::v(old), cc = WD::c(old);
     update_store<S, COMP>(v, cc, bb * g);
     return WD::make(v, cc);
 }
 
-template <class S, int COMP, bool FRC>
+template <class S, int COMP, bool FRC, bool NT>
 __device__ __forceinline__ typename Word<S, COMP>::type new_vy(const El2dDesc &d, int par,
                                                                 int i, int j)
 {
@@ -109,7 +121,7 @@ __device__ __forceinline__ typename Word<S, COMP>::type new_vy(const El2dDesc &d
     const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
     const int im = wrapx(i - 1, nx);
     const int row = j * pitch, q = row + i;
-    const W old = gmem((const W *)d.f[par][1])[q];
+    const W old = once<NT>((const W *)d.f[par][1], q);
     if (j >= ny - 1)
         return old;
     const float HW_GLOBAL *__restrict__ B = gmem(d.b);
@@ -143,14 +155,14 @@ __global__ __launch_bounds__(kThreads) void el2d_velocity_kernel(const El2dDesc 
     if (!c.valid)
         return;
     const int q = c.j * (int)d.pitch + c.i;
-    put((W *)d.f[par ^ 1][0], q, new_vx<S, COMP>(d, par, c.i, c.j));
-    put((W *)d.f[par ^ 1][1], q, new_vy<S, COMP, FRC>(d, par, c.i, c.j));
+    put((W *)d.f[par ^ 1][0], q, new_vx<S, COMP, true>(d, par, c.i, c.j));
+    put((W *)d.f[par ^ 1][1], q, new_vy<S, COMP, FRC, true>(d, par, c.i, c.j));
 }
 
 // The new stresses of cell (i, j) from the new velocities it needs (vx at
 // (i, j), (i-1, j), (i, j+1); vy at (i, j), (i, j-1), (i+1, j)) given as
 // values, old stresses from set par, written to set par^1.
-template <class S, int COMP>
+template <class S, int COMP, bool NT>
 __device__ __forceinline__ void stress_update(const El2dDesc &d, int par, int i, int j,
                                               float vx_q, float vx_im, float vx_jp,
                                               float vy_q, float vy_dn, float vy_ip)
@@ -163,14 +175,14 @@ __device__ __forceinline__ void stress_update(const El2dDesc &d, int par, int i,
     const bool surface = j == 0 || j == ny - 1;
     const float ex = w * (vx_q - vx_im);
     const float ey = surface ? 0.0f : w * (vy_q - vy_dn);
-    const float l2m = gmem(d.l2m)[q], lam = gmem(d.lam)[q];
+    const float l2m = once<NT>(d.l2m, q), lam = once<NT>(d.lam, q);
     auto upd = [&](int f, float inc) {
-        const W old = gmem((const W *)d.f[par][f])[q];
+        const W old = once<NT>((const W *)d.f[par][f], q);
         auto v = WD::v(old), cc = WD::c(old);
         update_store<S, COMP>(v, cc, inc);
         put((W *)d.f[par ^ 1][f], q, WD::make(v, cc));
     };
-    auto keep = [&](int f) { put((W *)d.f[par ^ 1][f], q, gmem((const W *)d.f[par][f])[q]); };
+    auto keep = [&](int f) { put((W *)d.f[par ^ 1][f], q, once<NT>((const W *)d.f[par][f], q)); };
     upd(2, l2m * ex + lam * ey);
     if (!surface)
         upd(3, l2m * ey + lam * ex);
@@ -180,7 +192,7 @@ __device__ __forceinline__ void stress_update(const El2dDesc &d, int par, int i,
         const float a1 = vy_ip - vy_q;
         const float a2 = vx_jp - vx_q;
         const float g = w * (a1 + a2);
-        upd(4, gmem(d.mxy)[q] * g);
+        upd(4, once<NT>(d.mxy, q) * g);
     } else {
         keep(4);
     }
@@ -203,23 +215,23 @@ __global__ __launch_bounds__(kThreads) void el2d_fused_kernel(const El2dDesc d, 
     const int nx = (int)d.nx, ny = (int)d.ny;
     const int i = c.i, j = c.j;
     const int q = j * (int)d.pitch + i;
-    const W wx = new_vx<S, COMP>(d, par, i, j);
-    const W wy = new_vy<S, COMP, FRC>(d, par, i, j);
+    const W wx = new_vx<S, COMP, false>(d, par, i, j);
+    const W wy = new_vy<S, COMP, FRC, false>(d, par, i, j);
     put((W *)d.f[par ^ 1][0], q, wx);
     put((W *)d.f[par ^ 1][1], q, wy);
     auto V = [](W x) { return S::load(WD::v(x)); };
     const float vx_q = V(wx), vy_q = V(wy);
-    const float vx_im = V(new_vx<S, COMP>(d, par, wrapx(i - 1, nx), j));
+    const float vx_im = V(new_vx<S, COMP, false>(d, par, wrapx(i - 1, nx), j));
     // the rows above and below are read only off the surfaces (ey) and
     // above the last row (sxy); rows stay uniform across a wavefront
     float vy_dn = 0.0f, vx_jp = 0.0f, vy_ip = 0.0f;
     if (j > 0 && j < ny - 1)
-        vy_dn = V(new_vy<S, COMP, FRC>(d, par, i, j - 1));
+        vy_dn = V(new_vy<S, COMP, FRC, false>(d, par, i, j - 1));
     if (j < ny - 1) {
-        vx_jp = V(new_vx<S, COMP>(d, par, i, j + 1));
-        vy_ip = V(new_vy<S, COMP, FRC>(d, par, wrapx(i + 1, nx), j));
+        vx_jp = V(new_vx<S, COMP, false>(d, par, i, j + 1));
+        vy_ip = V(new_vy<S, COMP, FRC, false>(d, par, wrapx(i + 1, nx), j));
     }
-    stress_update<S, COMP>(d, par, i, j, vx_q, vx_im, vx_jp, vy_q, vy_dn, vy_ip);
+    stress_update<S, COMP, false>(d, par, i, j, vx_q, vx_im, vx_jp, vy_q, vy_dn, vy_ip);
 }
 
 // Two-pass step, second pass: the new stresses of one cell from the new
@@ -243,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void el2d_stress_kernel(const El2dDesc d,
     GW vx = gmem((const W *)d.f[par ^ 1][0]);
     GW vy = gmem((const W *)d.f[par ^ 1][1]);
     auto L = [](GW p, int idx) { return S::load(WD::v(p[idx])); };
-    stress_update<S, COMP>(d, par, i, j, L(vx, q), L(vx, row + im), L(vx, qup),
+    stress_update<S, COMP, true>(d, par, i, j, L(vx, q), L(vx, row + im), L(vx, qup),
                            L(vy, q), L(vy, qdn), L(vy, row + ip));
 }
 
