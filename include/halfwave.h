@@ -290,11 +290,14 @@ hw_status hw_plan_set_tile(hw_plan *plan, int32_t tile);
 
 /* Advance n plans (0 < n) by nsteps[i] steps each, batching all plans with
  * the same physics, order, storage and compensation into one launch per
- * time step that covers every tile of every such plan still running.  Each
+ * time step that covers every tile of every such plan still running (2D
+ * elastic plans: their launches per step, one plan after another, captured
+ * into the same graph).  Each
  * plan's results (fields, comps, energy trace) are bit-identical to
  * hw_advance(plan, nsteps[i], energy_every) on it alone.  Plans are
- * borrowed and must be distinct.  tile >= 0 selects the batched kernel's
- * tile shape (as hw_tile_info), -1 uses the first plan's.  Async. */
+ * borrowed and must be distinct.  tile >= 0 selects the kernel shape (as
+ * hw_tile_info; it must exist for every plan's physics, else HW_E_INVAL),
+ * -1 gives each group the shape set on its first plan.  Async. */
 hw_status hw_batch_advance(hw_plan *const *plans, int32_t n,
                            const int64_t *nsteps, int64_t energy_every,
                            int32_t tile, void *stream);
