@@ -262,8 +262,10 @@ int64_t hw_plan_step(const hw_plan *plan);
 
 /* Checkpoint: the state (fields, compensation terms, step count) as an
  * opaque byte blob; importing it into a plan of the same problem and
- * continuing gives bit-identical results to never having stopped.  The
- * energy trace is not part of the blob.  Both synchronise `stream`. */
+ * continuing gives bit-identical results to never having stopped.  Equal
+ * states export equal blobs, whatever the arenas held before (the row
+ * padding inside the blob is always zero).  The energy trace is not part of
+ * the blob.  Both synchronise `stream`. */
 hw_status hw_state_size(const hw_plan *plan, size_t *bytes);
 hw_status hw_state_export(hw_plan *plan, void *blob, size_t bytes,
                           void *stream);
