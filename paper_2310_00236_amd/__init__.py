@@ -317,15 +317,17 @@ class Plan:
         _check(lib().hw_state_import(self.handle, buf, len(blob), self._s(stream)))
 
     def set_source(self, ix: int, iy: int, samples, stream=None):
-        """Point source on the pressure at cell (ix, iy); step n adds
-        samples[n] (see hw_set_source).  An empty sample list removes it."""
+        """Point source at cell (ix, iy): on the pressure (acoustic), on vy
+        at (ix, iy + 1/2) (2D elastic); step n adds samples[n] (see
+        hw_set_source).  An empty sample list removes it."""
         a = np.ascontiguousarray(np.asarray(samples, dtype=np.float64).ravel())
         _check(lib().hw_set_source(self.handle, ix, iy,
                                    a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    len(a), self._s(stream)))
 
     def set_receivers(self, cells, stream=None):
-        """Record (p, vx, vy) at the given (ix, iy) cells after every step."""
+        """Record (p, vx, vy) -- 2D elastic: the five fields -- at the given
+        (ix, iy) cells after every step."""
         cells = list(cells)
         ix = np.ascontiguousarray([c[0] for c in cells] or [0], dtype=np.int64)
         iy = np.ascontiguousarray([c[1] for c in cells] or [0], dtype=np.int64)
