@@ -274,8 +274,9 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
 
 /* Kernel shapes the library was built with, by index.  tx by ty cells of
  * a plane per workgroup; tz planes per workgroup; kind:
- *   acoustic2d  0 = one tile per workgroup, 1 = a workgroup marches down a
- *               strip ty rows tall;
+ *   acoustic2d  0 = one tile per workgroup (4 wavefronts), 3 = the same
+ *               with 8 wavefronts, 1 = a workgroup marches down a strip ty
+ *               rows tall;
  *   elastic3d   0 = two passes per step (velocities, then stresses), one
  *               plane per workgroup; 2 = one fused pass per step, a
  *               workgroup walks a tx by ty column through tz planes;

@@ -123,7 +123,7 @@ template <class S, int COMP, int ORDER>
 static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
                             bool forced, int stencil, hipStream_t s)
 {
-    const dim3 grid(a.total_tiles), block(kThreads);
+    const dim3 grid(a.total_tiles), block(kThreads), block8(8 * 64);
     Ac2dOne o;
     if (one) {
         o.d = *one;
@@ -144,6 +144,15 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
             else                                                                  \
                 hipLaunchKernelGGL((ac2d_step_kernel<S, COMP, ORDER, V, T>),      \
                                    grid, block, 0, s, a);                         \
+        } else if constexpr (kTiles2D[n].kind == 3) {                             \
+            if (one)                                                              \
+                hipLaunchKernelGGL((ac2d_step1_kernel<S, COMP, ORDER, V, T,       \
+                                                      false, 0, 8>),              \
+                                   grid, block8, 0, s, o);                        \
+            else                                                                  \
+                hipLaunchKernelGGL((ac2d_step_kernel<S, COMP, ORDER, V, T,        \
+                                                     false, 0, 8>),               \
+                                   grid, block8, 0, s, a);                        \
         } else if constexpr (COMP == COMP_TWOSUM8) {                              \
             return hipErrorInvalidValue;   /* 8-bit words: tile kernels only */   \
         } else {                                                                  \
@@ -157,11 +166,12 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
         break;                                                                    \
     }
         HW_TILE(0) HW_TILE(1) HW_TILE(2) HW_TILE(3) HW_TILE(4) HW_TILE(5) HW_TILE(6)
+        HW_TILE(7) HW_TILE(8)
 #undef HW_TILE
     default:
         return hipErrorInvalidValue;
     }
-    static_assert(kNumTiles2D == 7, "update the tile dispatch");
+    static_assert(kNumTiles2D == 9, "update the tile dispatch");
     return hipGetLastError();
 }
 

@@ -274,15 +274,16 @@ __device__ __forceinline__ void record(const Ac2dDesc &d, const Forcing &f, int 
             gmem(d.rec)[(f.row * f.rn + r) * 3 + c] = (double)v * d.rec_scale;
 }
 
-// A workgroup of 4 wavefronts owns a tile of TX = 64*V by TY cells.  Each
-// wavefront handles whole tile rows (row r goes to wavefront r mod 4) and
+// A workgroup of NW wavefronts (4 or 8) owns a tile of TX = 64*V by TY
+// cells.  Each wavefront handles whole tile rows (row r goes to wavefront
+// r mod NW) and
 // each lane V adjacent cells of a row, so every field of a lane's cells is
 // one global access; the few halo columns of a row are handled by the first
 // lanes.  Rows are enumerated from a multiple of 4 below the halo so that a
 // row keeps the same wavefront and register slot in every region (a cell's
 // old pressure word, loaded with the pressure tile, is still in registers
 // when its update runs).
-template <class S, int COMP, int ORDER, int V, int TY, bool WX, bool FRC, int SP>
+template <class S, int COMP, int ORDER, int V, int TY, bool WX, bool FRC, int SP, int NW>
 __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                                           int y0, bool yin, float *ps, float *bs,
                                           float *vxs, float *vys)
@@ -300,13 +301,13 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     constexpr int PW = TX + 2 * H;
     constexpr int BW = TX + 2 * R;
     constexpr int VXW = TX + 2 * R - 1;       // vx columns [-R, TX+R-1)
-    constexpr int OP = 4 * cdiv(H, 4);        // first pressure row is -OP
-    constexpr int OB = 4 * cdiv(R, 4);        // first buoyancy / vy row is -OB
-    constexpr int KP = cdiv(TY + H + OP, 4);  // pressure rows [-H, TY+H)
-    constexpr int KB = cdiv(TY + R + OB, 4);  // buoyancy rows [-R, TY+R)
-    constexpr int KY = cdiv(TY + R - 1 + OB, 4);   // vy rows [-R, TY+R-1)
-    constexpr int KC = TY / 4;                // the tile's own rows
-    static_assert(TY % 4 == 0, "tile height must be a multiple of 4");
+    constexpr int OP = NW * cdiv(H, NW);        // first pressure row is -OP
+    constexpr int OB = NW * cdiv(R, NW);        // first buoyancy / vy row is -OB
+    constexpr int KP = cdiv(TY + H + OP, NW);  // pressure rows [-H, TY+H)
+    constexpr int KB = cdiv(TY + R + OB, NW);  // buoyancy rows [-R, TY+R)
+    constexpr int KY = cdiv(TY + R - 1 + OB, NW);   // vy rows [-R, TY+R-1)
+    constexpr int KC = TY / NW;                // the tile's own rows
+    static_assert(TY % NW == 0, "tile height must be a multiple of the wavefront count");
     const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
     const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
     using A = Sten<S, SP>;
@@ -405,7 +406,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     int8_t qx[KC][V], qy[KY][V], qpp[KC][V], qxh = 0;   // 8-bit words
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int ly = -OP + wv + 4 * k;
+        const int ly = -OP + wv + NW * k;
         if (ly >= -H && ly < TY + H)
             pw[k] = ldw(p_in, grow(ly) * pitch);
     }
@@ -413,7 +414,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
         ph = S::load(WD::v(p_in[grow(hp.ly) * pitch + gcol(hp.lx)]));
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        const int ly = -OB + wv + 4 * k;
+        const int ly = -OB + wv + NW * k;
         if (ly >= -R && ly < TY + R) {
             const int row = grow(ly) * pitch;
             if constexpr (!WX) {
@@ -437,7 +438,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     }
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int ly = wv + 4 * k;
+        const int ly = wv + NW * k;
         if (y0 + ly < ny) {
             const int row = (y0 + ly) * pitch;
             vxw[k] = ldw_nt(vx_in, row);
@@ -459,7 +460,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     }
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
-        const int ly = -OB + wv + 4 * k;
+        const int ly = -OB + wv + NW * k;
         if (ly >= -R && ly < TY + R - 1) {
             vyw[k] = ldw(vy_in, grow(ly) * pitch);
             if constexpr (C8)
@@ -470,7 +471,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     // ---- 2. old pressure and buoyancy to LDS
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const int ly = -OP + wv + 4 * k;
+        const int ly = -OP + wv + NW * k;
         if (ly >= -H && ly < TY + H) {
             float *r = ps + (ly + H) * PW + H;
 #pragma unroll
@@ -482,7 +483,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
         ps[(hp.ly + H) * PW + H + hp.lx] = ph;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        const int ly = -OB + wv + 4 * k;
+        const int ly = -OB + wv + NW * k;
         if (ly >= -R && ly < TY + R) {
             float *r = bs + (ly + R) * BW + R;
 #pragma unroll
@@ -514,7 +515,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     // ---- 3a. new vx: the lane's V cells of each own row, plus the halo
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int ly = wv + 4 * k;
+        const int ly = wv + NW * k;
         if (y0 + ly < ny) {
             AT inc[V];
 #pragma unroll
@@ -557,7 +558,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     // ---- 3b. new vy: the lane's V cells of rows [-R, TY+R-1)
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
-        const int ly = -OB + wv + 4 * k;
+        const int ly = -OB + wv + NW * k;
         if (ly >= -R && ly < TY + R - 1) {
             AT inc[V];
 #pragma unroll
@@ -606,7 +607,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     // ---- 4. new pressure on the lane's cells of each own row
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int ly = wv + 4 * k;
+        const int ly = wv + NW * k;
         if (y0 + ly < ny) {
             AT inc[V];
 #pragma unroll
@@ -632,7 +633,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
                     dv = A::r(dv + A::m(fc.s));
                 inc[i] = A::r(A::m(km[k][i]) * dv);
             }
-            CV &pc = pw[k + OP / 4];          // row ly's pressure words
+            CV &pc = pw[k + OP / NW];          // row ly's pressure words
             upd(pc, qpp[k], inc);
             if (fc.rn > 0) {
 #pragma unroll
@@ -927,7 +928,7 @@ struct TileLds {
     float vys[(TY + 2 * R - 1) * TX];        // new vy
 };
 
-template <class S, int COMP, int ORDER, int V, int TY, bool FRC, int SP>
+template <class S, int COMP, int ORDER, int V, int TY, bool FRC, int SP, int NW>
 __device__ __forceinline__ void ac2d_tile_entry(const Ac2dDesc &d, int par,
                                                 int tile, int ntx,
                                                 TileLds<S, COMP, ORDER, V, TY> &L)
@@ -941,27 +942,44 @@ __device__ __forceinline__ void ac2d_tile_entry(const Ac2dDesc &d, int par,
     const bool xin = x0 >= H && x0 + TX + H <= nx;
     const bool yin = y0 >= H && y0 + TY + H <= ny;
     if (xin)
-        ac2d_tile<S, COMP, ORDER, V, TY, false, FRC, SP>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
+        ac2d_tile<S, COMP, ORDER, V, TY, false, FRC, SP, NW>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
     else
-        ac2d_tile<S, COMP, ORDER, V, TY, true, FRC, SP>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
+        ac2d_tile<S, COMP, ORDER, V, TY, true, FRC, SP, NW>(d, par, x0, y0, yin, L.ps, L.bs, L.vxs, L.vys);
 }
 
-template <class S, int COMP, int ORDER, int V, int TY, bool FRC = false, int SP = 0>
-__global__ __launch_bounds__(kThreads) void ac2d_step_kernel(const Ac2dBatch a)
+// Occupancy hint of the step kernels.  A workgroup of 8 wavefronts puts two
+// on each SIMD, so occupancy steps between 6 and 8 waves per SIMD at 64
+// VGPRs.  The plain fp16/bf16 updates fit in 64 VGPRs without scratch when
+// asked to; the compensated and fp32 variants would spill, and keep the
+// compiler's choice.
+template <class S, int COMP, int NW>
+constexpr int step_min_waves()
+{
+    return NW == 8 && COMP == COMP_NONE && S::id != F32::id ? 8 : 1;
+}
+
+template <class S, int COMP, int ORDER, int V, int TY, bool FRC = false, int SP = 0,
+          int NW = 4>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(step_min_waves<S, COMP, NW>())))
+void ac2d_step_kernel(const Ac2dBatch a)
 {
     __shared__ TileLds<S, COMP, ORDER, V, TY> L;
     int32_t tile = xcd_tile(blockIdx.x, a.total_tiles);
     const int shot = find_shot(a, tile);
-    ac2d_tile_entry<S, COMP, ORDER, V, TY, FRC, SP>(*a.desc[shot], a.parity[shot],
+    ac2d_tile_entry<S, COMP, ORDER, V, TY, FRC, SP, NW>(*a.desc[shot], a.parity[shot],
                                            tile - a.tile_start[shot],
                                            a.tiles_x[shot], L);
 }
 
-template <class S, int COMP, int ORDER, int V, int TY, bool FRC = false, int SP = 0>
-__global__ __launch_bounds__(kThreads) void ac2d_step1_kernel(const Ac2dOne o)
+template <class S, int COMP, int ORDER, int V, int TY, bool FRC = false, int SP = 0,
+          int NW = 4>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(step_min_waves<S, COMP, NW>())))
+void ac2d_step1_kernel(const Ac2dOne o)
 {
     __shared__ TileLds<S, COMP, ORDER, V, TY> L;
-    ac2d_tile_entry<S, COMP, ORDER, V, TY, FRC, SP>(o.d, o.parity,
+    ac2d_tile_entry<S, COMP, ORDER, V, TY, FRC, SP, NW>(o.d, o.parity,
                                            xcd_tile(blockIdx.x, o.total_tiles),
                                            o.tiles_x, L);
 }

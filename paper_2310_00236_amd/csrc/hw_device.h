@@ -62,16 +62,14 @@ struct BF16 {
     __device__ __forceinline__ static float load(store_t x) {
         return __uint_as_float((uint32_t)x << 16);
     }
-    // Round-to-nearest-even on the bit pattern: add 0x7fff plus the lowest
-    // kept bit, keep the top 16 bits.  Carries propagate into the exponent,
-    // so values past the largest finite bf16 become infinity; NaNs are kept
-    // quiet.
+    // fp32 -> bf16 by the hardware conversion (one instruction on gfx950):
+    // round to nearest even under the default rounding mode, subnormals kept
+    // (fp32 denormals are enabled in these kernels), values past the largest
+    // finite bf16 become infinity, NaNs stay NaNs (payload unspecified).
+    // For every non-NaN input this equals the bit-pattern rounding "add
+    // 0x7fff plus the lowest kept bit, keep the top 16 bits".
     __device__ __forceinline__ static store_t store(float x) {
-        uint32_t u = __float_as_uint(x);
-        if ((u & 0x7fffffffu) > 0x7f800000u)
-            return (store_t)((u >> 16) | 0x40u);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return (store_t)(u >> 16);
+        return __builtin_bit_cast(store_t, (__bf16)opaque(x));
     }
     __device__ __forceinline__ static float rn(float x) { return load(store(x)); }
 };

@@ -103,8 +103,10 @@ struct El3dOne {
 
 // Tile shapes compiled into the library (x by y cells per workgroup, and
 // the z planes one workgroup walks through for the marching 3D kernel).
-//   2D kind 0: a workgroup owns a tx by ty tile;
+//   2D kind 0: a workgroup of 4 wavefronts owns a tx by ty tile;
 //   2D kind 1: a workgroup marches down a strip tx wide and ty rows tall;
+//   2D kind 3: as kind 0 with 8 wavefronts (two rows of the tile per
+//              wavefront fewer; faster for bf16 and fp32);
 //   3D kind 0: two passes (velocities, then stresses), one tx by ty tile of
 //              one z plane per workgroup;
 //   3D kind 2: one fused pass, a workgroup walks a tx by ty column through
@@ -114,7 +116,7 @@ struct TileShape { int tx, ty, kind, tz; };
 // 2D: the width is 64 lanes times 1, 2 or 4 cells per lane
 constexpr TileShape kTiles2D[] = {{64, 16, 0, 1}, {64, 32, 0, 1}, {128, 16, 0, 1},
                                   {64, 64, 1, 1}, {64, 128, 1, 1}, {128, 64, 1, 1},
-                                  {128, 128, 1, 1}};
+                                  {128, 128, 1, 1}, {64, 16, 3, 1}, {128, 16, 3, 1}};
 constexpr TileShape kTiles3D[] = {{64, 4, 0, 1},    {256, 1, 0, 1},   {64, 6, 2, 128},
                                   {64, 6, 2, 64},   {64, 6, 2, 512},  {64, 10, 2, 128},
                                   {64, 14, 2, 128}};

@@ -331,7 +331,7 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             // variants and 8-bit compensation words run on tile kernels
             const bool tile_only = forced || stencil != HW_STENCIL_F32 ||
                                    (p0->pb.comp == HW_COMP_TWOSUM8 &&
-                                    kTiles2D[tile].kind != 0);
+                                    kTiles2D[tile].kind == 1);
             const int t = tile_only ? 0 : tile;
             int64_t total = 0;
             for (int i = 0; i < m; ++i) {

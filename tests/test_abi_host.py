@@ -48,8 +48,9 @@ def test_cfl_bounds():
 def test_tiles_listed():
     t2, t3 = hw.tiles("acoustic2d"), hw.tiles("elastic3d")
     assert len(t2) >= 2 and len(t3) >= 2
-    assert all(tx % 64 == 0 and ty % 4 == 0 and tz == 1 and kind in (0, 1)
+    assert all(tx % 64 == 0 and ty % 4 == 0 and tz == 1 and kind in (0, 1, 3)
                for tx, ty, tz, kind in t2)
+    assert all(ty % 8 == 0 for tx, ty, tz, kind in t2 if kind == 3)
     assert all((kind == 0 and tx * ty == 256 and tz == 1) or
                (kind == 2 and tx == 64 and (ty + 2) % 4 == 0 and tz >= 1)
                for tx, ty, tz, kind in t3)
