@@ -131,6 +131,54 @@ def test_power_of_two_field_scale_is_exact():
     assert_bitexact(gc, {k: v / 1024.0 for k, v in wc.items()}, "scaled comps")
 
 
+@pytest.mark.parametrize("comp", ["none", "twosum"])
+def test_bf16_subnormal_range_bitexact(comp):
+    """bf16 has fp32's exponent range, so fields scaled to about 2^-120 put
+    part of the values and all compensation terms among the bf16 subnormals
+    (spacing 2^-133) and part of the fp32 stencil among the fp32 subnormals:
+    the rounding to bf16 keeps them, bit for bit as in the oracle."""
+    nx, ny = 70, 40
+    rho, kappa, c = layered_material(nx, ny, 107)
+    dt = 0.4 * hw.cfl_bound("acoustic2d", 4) / c
+    f = {k: v * 2.0 ** -120 for k, v in acoustic_fields(nx, ny, 108, "bf16").items()}
+    g, gc, _ = gpu_acoustic(nx, ny, 4, "bf16", comp, dt, rho, kappa, f, 20)
+    w, wc, _ = oracle_acoustic(nx, ny, 4, "bf16", comp, dt, rho, kappa, f, 20)
+    assert_bitexact(g, w, "bf16 subnormal range")
+    if comp != "none":
+        assert_bitexact(gc, wc, "bf16 subnormal range comps")
+    tiny = lambda a: np.any((a != 0) & (np.abs(a) < 2.0 ** -126))
+    for k in g:                                          # the range is exercised
+        assert tiny(g[k]) and np.any(np.abs(g[k]) >= 2.0 ** -126), k
+        assert comp == "none" or tiny(gc[k]), k
+
+
+@pytest.mark.parametrize("comp", ["none", "twosum"])
+def test_bf16_overflow_matches_oracle(comp):
+    """Fields near the top of the bf16 range, one step: some pressure
+    differences overflow fp32, some pressure sums are finite in fp32 but round
+    past the largest finite bf16 to infinity, and infinities of opposite sign
+    meet to make NaNs.  The GPU has
+    the oracle's infinities and NaN cells and its finite values bit for bit
+    (only the sign and payload of a NaN are left open)."""
+    nx, ny = 70, 40
+    rng = np.random.default_rng(109)
+    ones = np.ones((ny, nx))
+    dt = 0.4 * hw.cfl_bound("acoustic2d", 4)
+    f = {"p": 2.0 ** 127 * rng.uniform(-1.5, 1.5, (ny, nx)),
+         "vx": np.zeros((ny, nx)), "vy": np.zeros((ny, nx))}
+    g, gc, _ = gpu_acoustic(nx, ny, 4, "bf16", comp, dt, ones, ones, f, 1)
+    w, wc, _ = oracle_acoustic(nx, ny, 4, "bf16", comp, dt, ones, ones, f, 1)
+    pairs = [(g, w)] + ([(gc, wc)] if comp != "none" else [])
+    for got, want in pairs:
+        for k in want:
+            gn, wn = np.isnan(got[k]), np.isnan(want[k])
+            assert np.array_equal(gn, wn), k
+            assert np.array_equal(got[k][~gn], want[k][~wn]), k
+            assert np.array_equal(np.signbit(got[k][~gn]), np.signbit(want[k][~wn])), k
+    for k in g:
+        assert np.isinf(g[k]).any() and np.isfinite(g[k]).any(), k
+
+
 @pytest.mark.parametrize("storage,comp", [("f16", "twosum"), ("f32", "none"),
                                           ("f16", "none"), ("bf16", "none"),
                                           ("f16", "twosum8")])
