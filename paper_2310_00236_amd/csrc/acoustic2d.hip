@@ -38,20 +38,13 @@ __global__ void set_counter_kernel(int64_t *c, int64_t v)
         *c = v;
 }
 
-// Fixed-order block sum of one fp64 value per thread (thread 0 returns it).
 __device__ __forceinline__ double block_sum(double v, double *red)
 {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
-        __syncthreads();
-    }
-    return red[0];
+    return block_sum_f64<kThreads>(v, red);
 }
 
-// Energy of the state, one workgroup per grid row: per-cell terms in fp64
+// Energy of the state, one workgroup per grid row (each XCD takes a
+// contiguous band of rows): per-cell terms in fp64
 // (v^{n+1/2} recomputed in fp64 from the stored state), summed in an order
 // that depends only on the grid size.
 template <class S, int ORDER>
@@ -62,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void ac2d_energy_kernel(
     __shared__ double red[kThreads];
     const Ac2dDesc &d = *dd;
     const int64_t nx = d.nx, ny = d.ny, pitch = d.pitch;
-    const int64_t j = blockIdx.x;
+    const int64_t j = xcd_band<kNumXcd>(blockIdx.x, gridDim.x);
     const int64_t j1 = wrap1(j + 1, ny);
     const int64_t j2 = wrapn(j + 2, ny);
     const int64_t jm = wrap1(j - 1, ny);
@@ -105,10 +98,23 @@ __global__ __launch_bounds__(kThreads) void energy_finish_kernel(
     double *__restrict__ out, int32_t *__restrict__ flag)
 {
     __shared__ double red[kThreads];
-    double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kThreads)
-        acc += partial[i];
-    const double s = block_sum(acc, red);
+    // four independent chains per thread (element i goes to chain
+    // (i / kThreads) % 4), joined in a fixed order
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t i = threadIdx.x;
+    for (; i + 3 * kThreads < n; i += 4 * kThreads) {
+        a0 += partial[i];
+        a1 += partial[i + kThreads];
+        a2 += partial[i + 2 * kThreads];
+        a3 += partial[i + 3 * kThreads];
+    }
+    if (i < n)
+        a0 += partial[i];
+    if (i + kThreads < n)
+        a1 += partial[i + kThreads];
+    if (i + 2 * kThreads < n)
+        a2 += partial[i + 2 * kThreads];
+    const double s = block_sum((a0 + a1) + (a2 + a3), red);
     if (threadIdx.x == 0) {
         const double e = s * factor;
         *out = e;

@@ -280,17 +280,9 @@ __global__ __launch_bounds__(64) void el2d_record_kernel(const El2dDesc d, int p
     }
 }
 
-// Fixed-order block sum of one fp64 value per thread (thread 0 returns it).
 __device__ __forceinline__ double block_sum2(double v, double *red)
 {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
-        __syncthreads();
-    }
-    return red[0];
+    return block_sum_f64<kThreads>(v, red);
 }
 
 // Energy of the state, one workgroup per row, fp64 per cell: h_j (vx^- vx^+
@@ -304,7 +296,7 @@ __global__ __launch_bounds__(kThreads) void el2d_energy_kernel(
     __shared__ double red[kThreads];
     const El2dDesc &d = *dd;
     const int64_t nx = d.nx, ny = d.ny, pitch = d.pitch;
-    const int64_t j = blockIdx.x;
+    const int64_t j = xcd_band<kNumXcd>(blockIdx.x, gridDim.x);
     const double w = d.w;
     const T *f[5];
     for (int n = 0; n < 5; ++n)

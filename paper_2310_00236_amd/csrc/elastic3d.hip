@@ -587,14 +587,7 @@ __global__ __launch_bounds__(kThreads) void el3d_fused1_kernel(const El3dOne a, 
 
 __device__ __forceinline__ double block_sum3(double v, double *red)
 {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
-        __syncthreads();
-    }
-    return red[0];
+    return block_sum_f64<kThreads>(v, red);
 }
 
 // Energy of the elastic state, one workgroup per (j, k) row, fp64.
@@ -606,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void el3d_energy_kernel(
     __shared__ double red[kThreads];
     const El3dDesc &d = *dd;
     const int64_t nx = d.nx, ny = d.ny, nz = d.nz, pitch = d.pitch, slab = d.slab;
-    const int64_t r = blockIdx.x;
+    const int64_t r = xcd_band<kNumXcd>(blockIdx.x, gridDim.x);
     const int64_t k = r / ny, j = r % ny;
     const int64_t jp = wrap1(j + 1, ny), jm = wrap1(j - 1, ny);
     const int64_t kp = wrap1(k + 1, nz), km = wrap1(k - 1, nz);

@@ -249,6 +249,39 @@ __device__ __forceinline__ void update_store_d(typename S::store_t &v,
     update_sum_store<S, COMP>(v, c, y);
 }
 
+// Workgroup b of n renumbered so that each of NXCD dies, which receive the
+// workgroups of a launch round-robin, works through one contiguous range
+// (neighbouring rows or tiles then share that die's L2).
+template <int NXCD>
+__device__ __forceinline__ int32_t xcd_band(int32_t b, int32_t n)
+{
+    const int32_t per = n / NXCD, rem = n % NXCD;
+    const int32_t x = b % NXCD, r = b / NXCD;
+    return x * per + (x < rem ? x : rem) + r;
+}
+
+// ------------------------------------------------- fp64 workgroup sum
+//
+// Sum of one fp64 value per thread over a workgroup of NT threads, in an
+// order fixed by NT alone: a butterfly across each wavefront's 64 lanes
+// (lane 0 keeps its result), then the wavefront sums added in wavefront
+// order.  Every thread returns the total; red holds NT / 64 doubles and is
+// written once, so a kernel calls this at most once.
+template <int NT>
+__device__ __forceinline__ double block_sum_f64(double v, double *red)
+{
+    static_assert(NT % 64 == 0 && NT >= 64, "whole wavefronts");
+    for (int m = 32; m > 0; m >>= 1)
+        v = v + __shfl_xor(v, m, 64);
+    if ((threadIdx.x & 63u) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int w = 1; w < NT / 64; ++w)
+        s = s + red[w];
+    return s;
+}
+
 // ------------------------------------------ 8-bit compensation word
 //
 // With COMP_TWOSUM8 the TwoSum error t of a sum s (|t| <= ulp(s)/2, ulp the
