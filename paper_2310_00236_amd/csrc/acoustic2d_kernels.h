@@ -16,9 +16,7 @@ namespace hw {
 // contiguous range of tiles so that tiles sharing halos share an L2.
 __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n)
 {
-    int32_t per = n / kNumXcd, rem = n % kNumXcd;
-    int32_t x = b % kNumXcd, r = b / kNumXcd;
-    return x * per + (x < rem ? x : rem) + r;
+    return xcd_band<kNumXcd>(b, n);
 }
 
 template <class A>

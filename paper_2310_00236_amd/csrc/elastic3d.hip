@@ -23,9 +23,7 @@ namespace hw {
 
 __device__ __forceinline__ int32_t xcd_tile3(int32_t b, int32_t n)
 {
-    int32_t per = n / kNumXcd, rem = n % kNumXcd;
-    int32_t x = b % kNumXcd, r = b / kNumXcd;
-    return x * per + (x < rem ? x : rem) + r;
+    return xcd_band<kNumXcd>(b, n);
 }
 
 __device__ __forceinline__ int find_shot3(const El3dBatch &a, int32_t t)
