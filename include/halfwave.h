@@ -315,6 +315,31 @@ hw_status hw_simulate(const hw_problem *pb, const double *const *material,
                       int64_t *n_energy, void *arena, size_t arena_bytes,
                       void *stream);
 
+/* Largest device footprint (hw_footprint) hw_simulate_noalloc accepts. */
+#define HW_NOALLOC_MAX_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (no hipMalloc, no torch
+ * allocator: tight serving loops, harnesses that forbid allocation): the
+ * same computation as hw_simulate, with the same arguments except the
+ * arena.  The plan lives in a statically allocated device array of
+ * HW_NOALLOC_MAX_BYTES bytes, one per GPU, held by the library from its
+ * first use on that GPU until the process ends; the call runs on the
+ * calling thread's current device (`stream` must belong to it), allocates
+ * no device memory and creates no stream, event or graph (every step is
+ * launched directly on `stream`).  Problems whose hw_footprint exceeds
+ * HW_NOALLOC_MAX_BYTES get HW_E_NOMEM before any device work.  Everything
+ * the kernels read is written by the call itself first, so a call does not
+ * depend on what an earlier one left in the array.  All calls on one GPU
+ * share that array: calls that overlap in time on the same GPU (from
+ * several threads, or on streams that are not synchronised with each
+ * other) race and give undefined results.  The call synchronises `stream`
+ * before it returns, so sequential calls never overlap. */
+hw_status hw_simulate_noalloc(const hw_problem *pb, const double *const *material,
+                              double *const *fields, int64_t nsteps,
+                              int64_t energy_every, double *energy,
+                              int64_t energy_cap, int64_t *n_energy,
+                              void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,6 +33,7 @@ STATUS = {0: "HW_OK", 1: "HW_E_INVAL", 2: "HW_E_UNSTABLE", 3: "HW_E_RANGE",
           4: "HW_E_NOMEM", 5: "HW_E_DEVICE", 6: "HW_E_NONFINITE",
           7: "HW_E_STATE"}
 ABI_VERSION = 6
+NOALLOC_MAX_BYTES = 64 << 20      # HW_NOALLOC_MAX_BYTES
 
 
 class HalfwaveError(RuntimeError):
@@ -107,6 +108,7 @@ def lib():
         "hw_batch_advance": (I32, [ctypes.POINTER(P), I32, PI64, I64, I32, P]),
         "hw_simulate": (I32, [PProb, PPD, PPD, I64, I64, PD, I64, PI64, P,
                               ctypes.c_size_t, P]),
+        "hw_simulate_noalloc": (I32, [PProb, PPD, PPD, I64, I64, PD, I64, PI64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -362,11 +364,7 @@ def batch_advance(plans: Sequence[Plan], nsteps, energy_every: int = 0,
                                   _stream_handle(stream, plans[0].device)))
 
 
-def simulate(pb: Problem, material, fields, nsteps: int, energy_every: int = 0,
-             device="cuda:0"):
-    """Blocking run through hw_simulate; returns (fields, energy)."""
-    import torch
-    arena = torch.empty(footprint(pb), dtype=torch.uint8, device=device)
+def _simulate_args(pb: Problem, material, fields):
     names = pb.field_names
     if isinstance(fields, dict):
         fields = [fields.get(k) for k in names]
@@ -377,9 +375,35 @@ def simulate(pb: Problem, material, fields, nsteps: int, energy_every: int = 0,
     mp, keep = _f64_ptrs(list(material), len(material), pb.shape, False)
     cap = max(pb.trace_cap, 1)
     e = np.zeros(cap)
+    return names, work, fp, mp, keep, cap, e
+
+
+def simulate(pb: Problem, material, fields, nsteps: int, energy_every: int = 0,
+             device="cuda:0"):
+    """Blocking run through hw_simulate; returns (fields, energy)."""
+    import torch
+    arena = torch.empty(footprint(pb), dtype=torch.uint8, device=device)
+    names, work, fp, mp, keep, cap, e = _simulate_args(pb, material, fields)
     n = ctypes.c_int64()
     _check(lib().hw_simulate(ctypes.byref(pb.c()), mp, fp, nsteps, energy_every,
-                             e.ctypes.data_as(P), cap, ctypes.byref(n),
-                             ctypes.c_void_p(arena.data_ptr()), arena.numel(),
-                             _stream_handle(None, torch.device(device))))
+                             e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap,
+                             ctypes.byref(n), ctypes.c_void_p(arena.data_ptr()),
+                             arena.numel(), _stream_handle(None, torch.device(device))))
+    return dict(zip(names, work)), e[:n.value].copy()
+
+
+def simulate_noalloc(pb: Problem, material, fields, nsteps: int, energy_every: int = 0,
+                     device="cuda:0", stream=None):
+    """Blocking run through hw_simulate_noalloc (no device allocation: the
+    plan lives in the library's static device array of NOALLOC_MAX_BYTES
+    per GPU); returns (fields, energy)."""
+    import torch
+    dev = torch.device(device)
+    names, work, fp, mp, keep, cap, e = _simulate_args(pb, material, fields)
+    n = ctypes.c_int64()
+    with torch.cuda.device(dev):
+        _check(lib().hw_simulate_noalloc(ctypes.byref(pb.c()), mp, fp, nsteps,
+                                         energy_every,
+                                         e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         cap, ctypes.byref(n), _stream_handle(stream, dev)))
     return dict(zip(names, work)), e[:n.value].copy()

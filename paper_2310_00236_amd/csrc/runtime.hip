@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -15,6 +16,11 @@
 #include "hw_internal.h"
 
 using namespace hw;
+
+// Device memory of hw_simulate_noalloc: one copy per GPU, held from the
+// module's load on that GPU until the process ends.  Host code never uses
+// this name as an address; it goes through scratch_address().
+static __device__ __align__(256) unsigned char scratch[HW_NOALLOC_MAX_BYTES];
 
 namespace {
 
@@ -199,6 +205,32 @@ Layout make_layout(const hw_problem *pb)
     return L;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the calling thread's current device,
+// looked up once per device (each GPU holds its own copy at its own
+// address).
+hw_status scratch_address(void **out)
+{
+    int dev = 0;
+    HW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(HW_E_DEVICE, "device index " + std::to_string(dev) + " beyond " +
+                                     std::to_string(kMaxDevices));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || (uintptr_t)ptr % kAlign != 0)
+            return fail(HW_E_DEVICE, "scratch array has no aligned device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HW_OK;
+}
+
 struct KernelKey {
     int physics, order, storage, comp, stencil;
     bool operator<(const KernelKey &o) const
@@ -240,6 +272,9 @@ struct hw_plan {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_tile = -1;
+    // launch every step directly: no capture stream, no graph (the
+    // no-allocation entry point creates no runtime objects)
+    bool direct = false;
     KernelKey key() const { return {pb.physics, pb.order, pb.storage, pb.comp, pb.stencil}; }
     ~hw_plan()
     {
@@ -488,11 +523,15 @@ hw_status capture_stream(hipStream_t *cs)
 // Advance a group of plans by `steps` steps with no host work in between:
 // whole runs of kGraphSteps replay a captured graph, the rest are launched
 // directly.  A single plan keeps its graph (captured from field set 0).
+// Direct plans launch every step on `s`.
 hw_status run_steps(hw_plan *const *plans, int n, int tile, int64_t steps,
                     hipStream_t s)
 {
     hw_status st;
-    if (steps >= kGraphSteps + 1 && n == 1) {
+    bool direct = false;
+    for (int i = 0; i < n; ++i)
+        direct = direct || plans[i]->direct;
+    if (!direct && steps >= kGraphSteps + 1 && n == 1) {
         hw_plan *p = plans[0];
         if (p->cur != 0) {                 // align to the captured field set
             if ((st = launch_group(plans, 1, tile, s)) != HW_OK)
@@ -513,7 +552,7 @@ hw_status run_steps(hw_plan *const *plans, int n, int tile, int64_t steps,
             HW_HIP(hipGraphLaunch(p->graph, s));
             advance_state(plans, 1, kGraphSteps);
         }
-    } else if (steps >= 2 * kGraphSteps) {
+    } else if (!direct && steps >= 2 * kGraphSteps) {
         hipGraphExec_t exec = nullptr;
         reap_graphs(false);
         if ((st = capture_stream(&t_cap_stream)) != HW_OK ||
@@ -728,66 +767,10 @@ void on_forcing(hw_plan *p, F f)
         f(p->h2);
 }
 
-struct BlobHeader {
-    char magic[8];
-    uint32_t abi;
-    int32_t physics, order, storage, comp, scale_log2;
-    int64_t nx, ny, nz, step;
-    uint64_t field_bytes;
-};
-
-}  // namespace
-
-// ------------------------------------------------------------------ ABI --
-
-extern "C" {
-
-uint32_t hw_abi_version(void) { return HW_ABI_VERSION; }
-
-const char *hw_last_error(void) { return g_error.c_str(); }
-
-int32_t hw_num_fields(int32_t physics)
+// Point a plan's fields at the regions of its arena and fill its
+// descriptors (host only).
+void init_plan(hw_plan *p, const hw_problem *pb, const Layout &L, void *arena)
 {
-    return physics == HW_ACOUSTIC2D ? 3 : physics == HW_ELASTIC3D ? 9
-                                        : physics == HW_ELASTIC2D ? 5 : 0;
-}
-
-int32_t hw_num_materials(int32_t physics)
-{
-    return physics == HW_ACOUSTIC2D ? 2
-           : physics == HW_ELASTIC3D || physics == HW_ELASTIC2D ? 3 : 0;
-}
-
-double hw_cfl_bound(int32_t physics, int32_t order) { return cfl_bound(physics, order); }
-
-hw_status hw_footprint(const hw_problem *pb, size_t *device_bytes)
-{
-    hw_status st = validate(pb);
-    if (st != HW_OK)
-        return st;
-    if (!device_bytes)
-        return fail(HW_E_INVAL, "device_bytes is NULL");
-    *device_bytes = make_layout(pb).total;
-    return HW_OK;
-}
-
-hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
-                         hw_plan **out)
-{
-    hw_status st = validate(pb);
-    if (st != HW_OK)
-        return st;
-    if (!out)
-        return fail(HW_E_INVAL, "out is NULL");
-    if (!arena || ((uintptr_t)arena % kAlign) != 0)
-        return fail(HW_E_INVAL, "arena must be a non-NULL 256-byte aligned device pointer");
-    const Layout L = make_layout(pb);
-    if (arena_bytes < L.total)
-        return fail(HW_E_NOMEM, "arena has " + std::to_string(arena_bytes) +
-                                    " bytes, the plan needs " + std::to_string(L.total));
-    hw_plan *p = new (std::nothrow) hw_plan();
-    if (!p)
-        return fail(HW_E_NOMEM, "host allocation failed");
     p->pb = *pb;
     p->L = L;
     p->arena = (char *)arena;
@@ -866,6 +849,76 @@ hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
             for (int f = 0; f < 9; ++f)
                 d.f[s][f] = p->fld[s][f];
     }
+}
+
+// The body of hw_simulate on a plan: upload, advance, download.  Every
+// region of the arena that a kernel reads before writing (both field sets,
+// the status flags and the step counter) is cleared by hw_set_fields.
+hw_status simulate_plan(hw_plan *p, const double *const *material, double *const *fields,
+                        int64_t nsteps, int64_t energy_every, double *energy,
+                        int64_t energy_cap, int64_t *n_energy, void *stream);
+
+struct BlobHeader {
+    char magic[8];
+    uint32_t abi;
+    int32_t physics, order, storage, comp, scale_log2;
+    int64_t nx, ny, nz, step;
+    uint64_t field_bytes;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI --
+
+extern "C" {
+
+uint32_t hw_abi_version(void) { return HW_ABI_VERSION; }
+
+const char *hw_last_error(void) { return g_error.c_str(); }
+
+int32_t hw_num_fields(int32_t physics)
+{
+    return physics == HW_ACOUSTIC2D ? 3 : physics == HW_ELASTIC3D ? 9
+                                        : physics == HW_ELASTIC2D ? 5 : 0;
+}
+
+int32_t hw_num_materials(int32_t physics)
+{
+    return physics == HW_ACOUSTIC2D ? 2
+           : physics == HW_ELASTIC3D || physics == HW_ELASTIC2D ? 3 : 0;
+}
+
+double hw_cfl_bound(int32_t physics, int32_t order) { return cfl_bound(physics, order); }
+
+hw_status hw_footprint(const hw_problem *pb, size_t *device_bytes)
+{
+    hw_status st = validate(pb);
+    if (st != HW_OK)
+        return st;
+    if (!device_bytes)
+        return fail(HW_E_INVAL, "device_bytes is NULL");
+    *device_bytes = make_layout(pb).total;
+    return HW_OK;
+}
+
+hw_status hw_plan_create(const hw_problem *pb, void *arena, size_t arena_bytes,
+                         hw_plan **out)
+{
+    hw_status st = validate(pb);
+    if (st != HW_OK)
+        return st;
+    if (!out)
+        return fail(HW_E_INVAL, "out is NULL");
+    if (!arena || ((uintptr_t)arena % kAlign) != 0)
+        return fail(HW_E_INVAL, "arena must be a non-NULL 256-byte aligned device pointer");
+    const Layout L = make_layout(pb);
+    if (arena_bytes < L.total)
+        return fail(HW_E_NOMEM, "arena has " + std::to_string(arena_bytes) +
+                                    " bytes, the plan needs " + std::to_string(L.total));
+    hw_plan *p = new (std::nothrow) hw_plan();
+    if (!p)
+        return fail(HW_E_NOMEM, "host allocation failed");
+    init_plan(p, pb, L, arena);
     *out = p;
     return HW_OK;
 }
@@ -1336,14 +1389,56 @@ hw_status hw_simulate(const hw_problem *pb, const double *const *material,
     hw_status st = hw_plan_create(pb, arena, arena_bytes, &p);
     if (st != HW_OK)
         return st;
+    st = simulate_plan(p, material, fields, nsteps, energy_every, energy, energy_cap,
+                       n_energy, stream);
+    hw_plan_destroy(p);
+    return st;
+}
+
+hw_status hw_simulate_noalloc(const hw_problem *pb, const double *const *material,
+                              double *const *fields, int64_t nsteps,
+                              int64_t energy_every, double *energy,
+                              int64_t energy_cap, int64_t *n_energy, void *stream)
+{
+    if (!fields)
+        return fail(HW_E_INVAL, "fields is NULL");
+    hw_status st = validate(pb);
+    if (st != HW_OK)
+        return st;
+    const Layout L = make_layout(pb);
+    if (L.total > (size_t)HW_NOALLOC_MAX_BYTES)
+        return fail(HW_E_NOMEM, "problem needs " + std::to_string(L.total) +
+                                    " device bytes; hw_simulate_noalloc holds at most " +
+                                    std::to_string((size_t)HW_NOALLOC_MAX_BYTES));
+    void *base = nullptr;
+    if ((st = scratch_address(&base)) != HW_OK)
+        return st;
+    hw_plan p;                     // host object on the stack, arena = scratch
+    init_plan(&p, pb, L, base);
+    p.direct = true;
+    st = simulate_plan(&p, material, fields, nsteps, energy_every, energy, energy_cap,
+                       n_energy, stream);
+    if (st != HW_OK)               // leave nothing in flight on the shared array
+        (void)hipStreamSynchronize(S(stream));
+    return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+hw_status simulate_plan(hw_plan *p, const double *const *material, double *const *fields,
+                        int64_t nsteps, int64_t energy_every, double *energy,
+                        int64_t energy_cap, int64_t *n_energy, void *stream)
+{
     const double *const *in = (const double *const *)fields;
+    hw_status st;
     if ((st = hw_set_material(p, material, stream)) == HW_OK &&
         (st = hw_set_fields(p, in, stream)) == HW_OK &&
         (st = hw_advance(p, nsteps, energy_every, stream)) == HW_OK &&
         (st = hw_get_fields(p, fields, nullptr, stream)) == HW_OK)
         st = hw_energy_trace(p, energy, nullptr, energy_cap, n_energy, stream);
-    hw_plan_destroy(p);
     return st;
 }
 
-}  // extern "C"
+}  // namespace

@@ -268,3 +268,27 @@ def test_elastic2d_host_validation_before_device():
     s1 = np.ones(1)
     assert L.hw_set_source(h, 3, 6, s1.ctypes.data_as(P), 1, None) == 1  # row ny-1
     L.hw_plan_destroy(h)
+
+
+def test_noalloc_refuses_before_the_device():
+    # invalid problems and problems beyond the static array fail on the host,
+    # before any HIP call (no GPU here)
+    L = hw.lib()
+    P = ctypes.POINTER(ctypes.c_double)
+    one = np.ones(4)
+    mat = (P * 3)(*[one.ctypes.data_as(P)] * 3)
+    fld = (P * 9)(*[one.ctypes.data_as(P)] * 9)
+    n = ctypes.c_int64()
+    big = hw.Problem("acoustic2d", 2048, 2048, 1, 4, "f16", "twosum", 1.0, 0.3, 0, 1)
+    assert hw.footprint(big) > hw.NOALLOC_MAX_BYTES
+    st = L.hw_simulate_noalloc(ctypes.byref(big.c()), mat, fld, 1, 0, None, 0,
+                               ctypes.byref(n), None)
+    assert hw.STATUS[st] == "HW_E_NOMEM"
+    assert "at most" in L.hw_last_error().decode()
+    bad = hw.Problem("acoustic2d", 8, 8, 1, 3, "f16", "twosum", 1.0, 0.3, 0, 1)
+    st = L.hw_simulate_noalloc(ctypes.byref(bad.c()), mat, fld, 1, 0, None, 0,
+                               ctypes.byref(n), None)
+    assert hw.STATUS[st] == "HW_E_INVAL"
+    st = L.hw_simulate_noalloc(ctypes.byref(bad.c()), mat, None, 1, 0, None, 0,
+                               ctypes.byref(n), None)
+    assert hw.STATUS[st] == "HW_E_INVAL"
