@@ -240,7 +240,12 @@ class Plan:
         return _stream_handle(stream, self.device)
 
     def close(self):
+        """Wait for the device's work, then destroy the plan (hw_plan_destroy
+        must not run while launches of the plan may still be pending, on any
+        stream the plan was driven on)."""
         if self.handle:
+            import torch
+            torch.cuda.synchronize(self.device)
             lib().hw_plan_destroy(self.handle)
             self.handle = None
 
