@@ -31,7 +31,8 @@ class Job:
     footprint: int               # device bytes while resident
     nsteps: int
     cells: int
-    payload: object = None       # executor-specific problem description
+    payload: object = None       # executor-specific problem description (or a
+                                 # callable returning it at admission)
     # filled in by the scheduler
     admitted: Optional[float] = None
     finished: Optional[float] = None
@@ -46,6 +47,8 @@ class Job:
 @dataclass
 class Stats:
     latencies: List[float] = field(default_factory=list)
+    queueing: List[float] = field(default_factory=list)    # arrival -> admitted
+    service: List[float] = field(default_factory=list)     # admitted -> finished
     cell_steps: int = 0
     wall: float = 0.0
     peak_bytes: int = 0
@@ -54,13 +57,19 @@ class Stats:
     rejected: int = 0
 
     def summary(self) -> dict:
-        lat = np.asarray(self.latencies) if self.latencies else np.zeros(1)
+        def arr(v):
+            return np.asarray(v) if v else np.zeros(1)
+        lat, q, sv = arr(self.latencies), arr(self.queueing), arr(self.service)
         return {
             "completed": len(self.latencies),
             "rejected": self.rejected,
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_latency_s": float(lat.mean()),
+            "p50_queueing_s": float(np.percentile(q, 50)),
+            "p99_queueing_s": float(np.percentile(q, 99)),
+            "p50_service_s": float(np.percentile(sv, 50)),
+            "p99_service_s": float(np.percentile(sv, 99)),
             "aggregate_glups": self.cell_steps / self.wall / 1e9 if self.wall else 0.0,
             "wall_s": self.wall,
             "peak_resident_bytes": self.peak_bytes,
@@ -78,12 +87,14 @@ class Scheduler:
       launch(jobs, steps_each)    start advancing resident jobs (async)
       wait()                      block until the launched chunk is done
       retire(job) -> result       copy results out and release memory
+                                  (GpuExecutor: (fields, energy, comps))
     clock() returns seconds since the stream started; idle(dt) waits for
     the next arrival when nothing is resident.
     """
 
     def __init__(self, executor, budget_bytes: int, chunk_steps: int,
-                 clock: Callable[[], float], idle: Callable[[float], None]):
+                 clock: Callable[[], float], idle: Callable[[float], None],
+                 on_retire: Optional[Callable[[Job], None]] = None):
         if budget_bytes <= 0 or chunk_steps <= 0:
             raise ValueError("budget and chunk must be positive")
         self.ex = executor
@@ -91,6 +102,7 @@ class Scheduler:
         self.chunk = chunk_steps
         self.clock = clock
         self.idle = idle
+        self.on_retire = on_retire
         self.done: List[Job] = []
 
     def run(self, jobs: Iterable[Job]) -> Stats:
@@ -134,6 +146,10 @@ class Scheduler:
                     resident.remove(j)
                     self.done.append(j)
                     st.latencies.append(j.latency)
+                    st.queueing.append(j.admitted - j.arrival)
+                    st.service.append(j.finished - j.admitted)
+                    if self.on_retire:
+                        self.on_retire(j)
             resident.extend(joining)
             st.max_resident = max(st.max_resident, len(resident))
             if not resident and not queue and pending:
@@ -144,7 +160,12 @@ class Scheduler:
 
 class GpuExecutor:
     """Runs jobs through libhalfwave: one plan (and arena) per resident job;
-    uploads on a copy stream, batched advances on the compute stream."""
+    uploads on a copy stream; each chunk advances every group of resident
+    jobs that share a kernel (physics, storage format, compensation) in one
+    batched call on that group's own stream, so the groups' launches
+    overlap on the device (all streams at the default priority)."""
+
+    max_streams = 4
 
     def __init__(self, device="cuda:0", energy_every: int = 0):
         import torch
@@ -154,13 +175,30 @@ class GpuExecutor:
         self.tuning = tuning
         self.torch = torch
         self.device = torch.device(device)
-        self.compute = torch.cuda.Stream(self.device)
         self.copy = torch.cuda.Stream(self.device)
+        self.streams = {}           # kernel group -> stream
+        self.busy = []              # streams with work in the current chunk
         self.energy_every = energy_every
         self.plans = {}
 
+    @staticmethod
+    def group(pb):
+        return (pb.physics, pb.order, pb.storage, pb.comp)
+
+    def _stream(self, key):
+        if key not in self.streams:
+            if len(self.streams) < self.max_streams:
+                self.streams[key] = self.torch.cuda.Stream(self.device)
+            else:                   # more groups than streams: share round-robin
+                pool = list(dict.fromkeys(self.streams.values()))
+                self.streams[key] = pool[len(self.streams) % len(pool)]
+        return self.streams[key]
+
     def admit(self, job: Job):
-        pb, material, fields = job.payload
+        # the payload is (problem, material, fields), or a callable that
+        # draws them when the request is admitted
+        payload = job.payload() if callable(job.payload) else job.payload
+        pb, material, fields = payload
         plan = self.hw.Plan(pb, device=self.device)
         plan.set_tile(self.tuning.best_tile(pb.physics, pb.order, pb.storage,
                                             pb.comp, pb.nx, pb.ny, pb.nz))
@@ -169,20 +207,29 @@ class GpuExecutor:
         self.plans[job.id] = plan
 
     def launch(self, jobs, steps):
-        plans = [self.plans[j.id] for j in jobs]
-        self.hw.batch_advance(plans, list(steps), self.energy_every,
-                              stream=self.compute)
+        groups = {}
+        for j, s in zip(jobs, steps):
+            plan = self.plans[j.id]
+            groups.setdefault(self.group(plan.pb), []).append((plan, s))
+        self.busy = []
+        for key, members in groups.items():
+            stream = self._stream(key)
+            self.hw.batch_advance([m[0] for m in members], [m[1] for m in members],
+                                  self.energy_every, stream=stream)
+            self.busy.append(stream)
 
     def wait(self):
-        self.compute.synchronize()
+        for stream in self.busy:
+            stream.synchronize()
+        self.busy = []
 
     def retire(self, job: Job):
         plan = self.plans.pop(job.id)
-        out = plan.get_fields(stream=self.compute)
-        energy = plan.energy_trace(stream=self.compute)[0] \
-            if self.energy_every else None
+        stream = self._stream(self.group(plan.pb))
+        out, comps = plan.get_fields(comps=True, stream=stream)
+        energy = plan.energy_trace(stream=stream)[0] if self.energy_every else None
         plan.close()
-        return out, energy
+        return out, energy, comps
 
 
 def job_for(req, problem, material, fields, trace_cap=0) -> Job:
@@ -193,16 +240,18 @@ def job_for(req, problem, material, fields, trace_cap=0) -> Job:
 
 
 def serve(jobs: List[Job], budget_bytes: int, chunk_steps: int = 200,
-          device="cuda:0", energy_every: int = 0, realtime: bool = True):
+          device="cuda:0", energy_every: int = 0, realtime: bool = True,
+          on_retire: Optional[Callable[[Job], None]] = None):
     """Run a request stream on the GPU; returns (stats summary, jobs done).
 
-    realtime=False treats every request as arrived at time 0."""
+    realtime=False treats every request as arrived at time 0; on_retire is
+    called with each finished job."""
     ex = GpuExecutor(device, energy_every)
     if not realtime:
         for j in jobs:
             j.arrival = 0.0
     t0 = time.perf_counter()
     sched = Scheduler(ex, budget_bytes, chunk_steps,
-                      lambda: time.perf_counter() - t0, time.sleep)
+                      lambda: time.perf_counter() - t0, time.sleep, on_retire)
     st = sched.run(jobs)
     return st.summary(), sched.done

@@ -1,8 +1,8 @@
 """Parity at the benchmark's full sizes, in the launch configurations the
 benchmark times: the 512^3 elastic workload in its tuned (fused) kernel
-shape, checked cell by cell on sampled cells against the oracle on local
-periodic patches; and the 64-shot batched workload, every shot
-bit-identical batched and alone."""
+shape, checked cell by cell against the oracle on whole planes around the
+kernel's z-segment boundaries and on patches around random cells; and the
+64-shot batched workload, every shot bit-identical batched and alone."""
 import sys
 import time
 
@@ -20,34 +20,51 @@ FIELDS = oracle.ELASTIC_FIELDS
 
 
 def _decode_state(plan, blob):
-    """Split an fp16 + compensation state blob into per-field value and
-    compensation arrays [nz, ny, nx] (the blob holds each field's padded
-    words, (value, compensation) side by side, after a fixed header)."""
+    """Split a state blob into per-field value and compensation arrays
+    [nz, ny, nx] (the blob holds each field's padded words after a fixed
+    header: fp32 values, or (fp16 value, fp16 compensation) side by side)."""
     pb = plan.pb
     pitch = (pb.nx + 63) // 64 * 64
     n = pitch * pb.ny * pb.nz
-    field_bytes = (n * 4 + 255) // 256 * 256
+    comp = pb.comp != "none"
+    words = 2 if comp else 1
+    dt = np.float32 if pb.storage == "f32" else np.float16
+    esz = np.dtype(dt).itemsize
+    field_bytes = (n * esz * words + 255) // 256 * 256
     head = len(blob) - len(FIELDS) * field_bytes
     vals, comps = {}, {}
     for i, k in enumerate(FIELDS):
-        w = np.frombuffer(blob, dtype=np.float16, count=2 * n,
-                          offset=head + i * field_bytes).reshape(pb.nz, pb.ny, pitch, 2)
+        w = np.frombuffer(blob, dtype=dt, count=words * n,
+                          offset=head + i * field_bytes).reshape(pb.nz, pb.ny, pitch, words)
         vals[k] = w[:, :, :pb.nx, 0]
-        comps[k] = w[:, :, :pb.nx, 1]
+        comps[k] = w[:, :, :pb.nx, 1] if comp else None
     return vals, comps
 
 
-def test_elastic_512_sampled_one_step():
-    """512^3 smooth medium, fp16 + TwoSum, the tuned kernel shape: after 20
-    steps, one more step is checked on 40 sampled cells (and the corners)
-    against the oracle run on 9^3 periodic patches around them (one step of
-    the scheme reaches 2 cells)."""
+def _segment_planes(tile, n):
+    """z planes where the tuned fused kernel's segments meet (a segment of
+    tz planes starts with warm-up planes whose velocities it recomputes)."""
+    tz = hw.tiles("elastic3d")[tile][2]
+    return sorted({(b + d) % n for b in range(0, n, tz) for d in (-1, 0)})
+
+
+@pytest.mark.parametrize("storage,comp", [("f16", "twosum"), ("f32", "none")])
+def test_elastic_512_one_step_on_segment_boundary_slabs(storage, comp):
+    """512^3 smooth medium in the tuned (fused, z-marching) kernel shape, as
+    the benchmark times it: after 20 steps, one more step is compared with
+    the oracle on whole planes -- the five planes around every boundary
+    between the kernel's z segments (wrap-around included), so every column
+    edge (x = 63/64, y where the 64 x ty columns meet) of every segment's
+    warm-up and last planes -- and on 9^3 patches around 40 random cells.
+    The oracle runs periodic slabs of 9 planes; the middle five depend only
+    on planes inside the slab (one step reaches two cells)."""
     n = 512
     w = workloads.smooth3d(n, nsteps=20)
-    pb = hw.Problem("elastic3d", n, n, n, 2, "f16", "twosum", w.dx, w.dt, 0, 0)
+    pb = hw.Problem("elastic3d", n, n, n, 2, storage, comp, w.dx, w.dt, 0, 0)
     plan = hw.Plan(pb)
-    plan.set_tile(tuning.best_tile("elastic3d", 2, "f16", "twosum", n, n, n))
-    assert hw.tiles("elastic3d")[plan_tile(plan)][3] == 2      # the fused kernel kind
+    tile = tuning.best_tile("elastic3d", 2, storage, comp, n, n, n)
+    plan.set_tile(tile)
+    assert hw.tiles("elastic3d")[tile][3] == 2      # the fused kernel kind
     plan.set_material([w.rho, w.lam, w.mu])
     plan.set_fields(w.fields())
     plan.advance(w.nsteps)
@@ -55,22 +72,48 @@ def test_elastic_512_sampled_one_step():
     plan.advance(1)
     after = _decode_state(plan, plan.export_state())
     plan.close()
-    rng = np.random.default_rng(9)
-    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 255)] + \
-        [tuple(int(v) for v in rng.integers(0, n, size=3)) for _ in range(40)]
-    m = 4
-    for (k, j, i) in pts:
-        idx = np.ix_(np.arange(k - m, k + m + 1) % n, np.arange(j - m, j + m + 1) % n,
-                     np.arange(i - m, i + m + 1) % n)
+
+    def check(kidx, jidx, iidx, centre, local, label):
+        """Run the oracle on the periodic patch kidx x jidx x iidx of the
+        state and compare the GPU's cells `centre` (global index arrays per
+        axis) with the oracle's cells `local` (patch index arrays)."""
+        idx = np.ix_(kidx, jidx, iidx)
         f = {key: before[0][key][idx].astype(np.float64) for key in FIELDS}
-        c = {key: before[1][key][idx].astype(np.float64) for key in FIELDS}
-        s = 2 * m + 1
-        o, oc, _ = oracle.elastic3d(s, s, s, w.dx, w.dt, w.rho[idx], w.lam[idx],
-                                    w.mu[idx], f, storage="f16", stencil="f32",
-                                    comp="twosum", comps=c, nsteps=1)
+        c = {key: before[1][key][idx].astype(np.float64) for key in FIELDS} \
+            if comp != "none" else None
+        o, oc, _ = oracle.elastic3d(len(iidx), len(jidx), len(kidx), w.dx, w.dt,
+                                    w.rho[idx], w.lam[idx], w.mu[idx], f,
+                                    storage=storage, stencil="f32", comp=comp,
+                                    comps=c, nsteps=1)
         for key in FIELDS:
-            assert float(after[0][key][k, j, i]) == o[key][m, m, m], (key, k, j, i)
-            assert float(after[1][key][k, j, i]) == oc[key][m, m, m], (key, k, j, i)
+            got = after[0][key][np.ix_(*centre)].astype(np.float64)
+            want = o[key][np.ix_(*local)]
+            assert np.array_equal(got, want) and \
+                np.array_equal(np.signbit(got), np.signbit(want)), (key, label)
+            if comp != "none":
+                got = after[1][key][np.ix_(*centre)].astype(np.float64)
+                want = oc[key][np.ix_(*local)]
+                assert np.array_equal(got, want) and \
+                    np.array_equal(np.signbit(got), np.signbit(want)), ("comp", key, label)
+
+    full = np.arange(n)
+    done = set()
+    for k0 in _segment_planes(tile, n):
+        if k0 in done:
+            continue
+        kidx = np.arange(k0 - 4, k0 + 5) % n
+        mid = kidx[2:7]
+        done.update(int(k) for k in mid)
+        check(kidx, full, full, (mid, full, full), (np.arange(2, 7), full, full),
+              f"planes {list(mid)}")
+    rng = np.random.default_rng(9)
+    m = 4
+    one = np.array([m])
+    for _ in range(40):
+        k, j, i = (int(v) for v in rng.integers(0, n, size=3))
+        ax = [np.arange(c - m, c + m + 1) % n for c in (k, j, i)]
+        check(*ax, (np.array([k]), np.array([j]), np.array([i])), (one, one, one),
+              f"cell {(k, j, i)}")
 
 
 def plan_tile(plan):
