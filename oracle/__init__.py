@@ -24,6 +24,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# AddressSanitizer + UndefinedBehaviorSanitizer build of the same source,
+# loaded instead when ORACLE_SANITIZE=1 (the process must preload the
+# sanitizer runtimes, see sanitizer_env())
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"]
 
 FORMATS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 COMPS = {"none": 0, "fast2sum": 1, "twosum": 2, "twosum8": 3}
@@ -37,14 +43,32 @@ CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
           "-fPIC", "-shared", "-std=c11"]
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so next to it and return the path."""
-    if force or not os.path.exists(_LIB) or \
-            os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile oracle.c into liboracle.so next to it (liboracle_san.so with
+    the sanitizers) and return the path."""
+    out = _LIB_SAN if sanitize else _LIB
+    flags = [f for f in CFLAGS if f != "-O2"] + SAN_FLAGS if sanitize else CFLAGS
+    if force or not os.path.exists(out) or \
+            os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *flags, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def sanitizer_env() -> dict:
+    """Environment for a child process that loads the sanitized oracle: the
+    ASan and UBSan runtimes preloaded (the Python interpreter itself is not
+    instrumented), leak checks off (the interpreter's own allocations)."""
+    def rt(name):
+        return subprocess.check_output(["gcc", f"-print-file-name={name}"],
+                                       text=True).strip()
+    env = dict(os.environ)
+    env.update({"ORACLE_SANITIZE": "1",
+                "LD_PRELOAD": f"{rt('libasan.so')}:{rt('libubsan.so')}",
+                "ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+                "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1"})
+    return env
 
 
 _lib = None
@@ -53,8 +77,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        L = ctypes.CDLL(_LIB)
+        san = os.environ.get("ORACLE_SANITIZE") == "1"
+        L = ctypes.CDLL(build(force=False, sanitize=san))
         D = ctypes.c_double
         Lg = ctypes.c_long
         I = ctypes.c_int
@@ -70,6 +94,8 @@ def lib():
         L.orc_twosum.argtypes = [D, D, I, P, P]
         L.orc_eft_check.restype = Lg
         L.orc_eft_check.argtypes = [I, I, P, Lg, P, Lg, I]
+        L.orc_eft_exhaustive.restype = None
+        L.orc_eft_exhaustive.argtypes = [I, Lg, Lg, ctypes.POINTER(ctypes.c_long)]
         L.orc_quantize_comp.restype = D
         L.orc_quantize_comp.argtypes = [D, D, I]
         L.orc_max_threads.restype = I
@@ -140,6 +166,20 @@ def eft_check(fmt: str, which: int, a, b, require_order: bool) -> int:
     b = _f64(b, np.shape(b))
     return int(lib().orc_eft_check(FORMATS[fmt], which, _ptr(a), a.size,
                                    _ptr(b), b.size, int(require_order)))
+
+
+EFT_COUNTS = ("pairs", "twosum_not_exact", "twosum_overflow", "ordered_pairs",
+              "fast2sum_ordered_not_exact", "fast2sum_ordered_overflow",
+              "fast2sum_unordered_not_exact", "sum_overflow")
+
+
+def eft_exhaustive(fmt: str, a_lo: int = 0, a_hi: int = 1 << 16) -> dict:
+    """Exactness of both compensated sums over every pair of finite values
+    of a 16-bit format ('f16' or 'bf16') whose first operand's bit pattern
+    lies in [a_lo, a_hi) (see orc_eft_exhaustive for the counts)."""
+    out = (ctypes.c_long * 8)()
+    lib().orc_eft_exhaustive(FORMATS[fmt], a_lo, a_hi, out)
+    return dict(zip(EFT_COUNTS, list(out)))
 
 
 # ---------------------------------------------------------------- solvers --

@@ -117,8 +117,8 @@ void orc_round_array(const double *x, double *y, long n, int fmt)
 /* Compensated sums (Sec. 4, Code 1 and Code 2), in format fmt.             */
 /* ------------------------------------------------------------------------ */
 
-/* 3-operation form: the sum s and the part t of b lost in forming it.
- * Error free when |a| >= |b|. */
+/* 3-operation form (Code 1; Dekker's Fast2Sum): the sum s and the part t
+ * of b lost in forming it.  Error free when |a| >= |b|. */
 void orc_fast2sum(double a, double b, int fmt, double *s, double *t)
 {
     double ss = orc_round(a + b, fmt);
@@ -127,7 +127,8 @@ void orc_fast2sum(double a, double b, int fmt, double *s, double *t)
     *s = ss;
 }
 
-/* 6-operation form: error free for any ordering of |a| and |b|. */
+/* 6-operation form (Code 2; the TwoSum of Knuth and Moller): error free
+ * for any ordering of |a| and |b|. */
 void orc_twosum(double a, double b, int fmt, double *s, double *t)
 {
     double ss = orc_round(a + b, fmt);
@@ -177,6 +178,96 @@ double orc_quantize_comp(double t, double s, int fmt)
     return ldexp(q * u, -7);
 }
 
+/* Whether the pair (s, t) holds exactly the sum x + y.  Two exact sums of
+ * doubles are equal iff their canonical double-double forms (fp64 TwoSum:
+ * the rounded sum and the exact remainder) are equal; exact for all the
+ * formats here because their values are multiples of 2^-149. */
+static int sum_is_exact(double x, double y, double s, double t)
+{
+    double h1, l1, h2, l2;
+    orc_twosum(x, y, FMT_F64, &h1, &l1);
+    orc_twosum(s, t, FMT_F64, &h2, &l2);
+    return h1 == h2 && l1 == l2;
+}
+
+/* Value of a 16-bit pattern: fp16 (1 sign, 5 exponent and 10 fraction
+ * bits, exponent bias 15, subnormals below 2^-14) or bf16 (the upper half
+ * of an fp32 pattern: 1 sign, 8 exponent, 7 fraction bits, bias 127).
+ * *finite is 0 for infinities and NaNs. */
+static double decode16(unsigned bits, int fmt, int *finite)
+{
+    const int sign = (bits >> 15) & 1;
+    int ebits, fbits, bias;
+    if (fmt == FMT_F16) {
+        ebits = 5; fbits = 10; bias = 15;
+    } else {
+        ebits = 8; fbits = 7; bias = 127;
+    }
+    const unsigned e = (bits >> fbits) & ((1u << ebits) - 1);
+    const unsigned f = bits & ((1u << fbits) - 1);
+    *finite = e != (1u << ebits) - 1;
+    double v;
+    if (e == 0)
+        v = ldexp((double)f, 1 - bias - fbits);           /* zero, subnormal */
+    else
+        v = ldexp((double)(f | (1u << fbits)), (int)e - bias - fbits);
+    return sign ? -v : v;
+}
+
+/* Exhaustive exactness of the two compensated sums (Sec. 4) in a 16-bit
+ * format (fp16 or bf16): every pair (a, b) of finite values, a's bit
+ * pattern in [a_lo, a_hi), b over all 2^16 patterns.  counts (8 entries):
+ *   [0] pairs checked
+ *   [1] pairs where the 6-operation sum is not error free
+ *   [2] pairs where an operation of the 6-operation sum overflows (s or t
+ *       not finite; there is then no finite split)
+ *   [3] ordered pairs (|a| >= |b|), the condition of the 3-operation sum
+ *   [4] ordered pairs where the 3-operation sum is not error free
+ *   [5] ordered pairs where the 3-operation sum overflows
+ *   [6] unordered pairs (|a| < |b|) where the 3-operation sum is finite
+ *       and not error free
+ *   [7] pairs where the rounded sum a + b itself overflows */
+void orc_eft_exhaustive(int fmt, long a_lo, long a_hi, long *counts)
+{
+    long c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0;
+#pragma omp parallel for schedule(dynamic, 16) \
+    reduction(+ : c0, c1, c2, c3, c4, c5, c6, c7)
+    for (long ia = a_lo; ia < a_hi; ++ia) {
+        int fa;
+        const double x = decode16((unsigned)ia, fmt, &fa);
+        if (!fa)
+            continue;
+        for (unsigned ib = 0; ib < 65536u; ++ib) {
+            int fb;
+            const double y = decode16(ib, fmt, &fb);
+            if (!fb)
+                continue;
+            ++c0;
+            if (!isfinite(orc_round(x + y, fmt)))
+                ++c7;
+            double s, t;
+            orc_twosum(x, y, fmt, &s, &t);
+            if (!isfinite(s) || !isfinite(t))
+                ++c2;
+            else if (!sum_is_exact(x, y, s, t))
+                ++c1;
+            orc_fast2sum(x, y, fmt, &s, &t);
+            const int finite = isfinite(s) && isfinite(t);
+            if (fabs(x) >= fabs(y)) {
+                ++c3;
+                if (!finite)
+                    ++c5;
+                else if (!sum_is_exact(x, y, s, t))
+                    ++c4;
+            } else if (finite && !sum_is_exact(x, y, s, t)) {
+                ++c6;
+            }
+        }
+    }
+    counts[0] = c0; counts[1] = c1; counts[2] = c2; counts[3] = c3;
+    counts[4] = c4; counts[5] = c5; counts[6] = c6; counts[7] = c7;
+}
+
 /* Exactness check used by the tests: counts pairs (a[i], b[j]) with
  * a + b != s + t.  Equality of two exact sums of doubles is decided by
  * comparing their canonical double-double forms (fp64 TwoSum yields the
@@ -201,10 +292,7 @@ long orc_eft_check(int fmt, int which, const double *a, long na,
                 orc_twosum(x, y, fmt, &s, &t);
             if (!isfinite(s) || !isfinite(t))
                 continue;   /* an operation overflowed: no finite split */
-            double h1, l1, h2, l2;
-            orc_twosum(x, y, FMT_F64, &h1, &l1);
-            orc_twosum(s, t, FMT_F64, &h2, &l2);
-            if (h1 != h2 || l1 != l2)
+            if (!sum_is_exact(x, y, s, t))
                 ++bad;
         }
     }

@@ -258,3 +258,46 @@ def test_recursive_sum_stagnation_and_compensation():
     exact = n * delta
     assert abs(s - exact) <= 2.0 ** -10      # one ulp at [1, 2)
     assert abs((s + c) - exact) <= 2.0 ** -22
+
+
+# ------------------------------------------- exhaustive compensated sums --
+
+EFT_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "eft_exhaustive.json")
+
+
+@pytest.mark.parametrize("fmt,finite", [("f16", 65536 - 2 * 1024), ("bf16", 65536 - 2 * 128)])
+def test_compensated_sums_exhaustive_record(fmt, finite):
+    """Every pair of finite fp16 values and every pair of finite bf16 values
+    (2^32 pairs less the non-finite ones), run by make_eft_exhaustive.py:
+    the 6-operation sum (Code 2) is error free on every pair whose
+    operations stay finite, the 3-operation sum (Code 1) on every such
+    ordered pair |a| >= |b| (Sec. 4), and it fails on some unordered ones.
+    Pairs where an operation overflows are counted apart."""
+    rec = json.load(open(EFT_GOLDEN))[fmt]
+    assert rec["pairs"] == finite * finite
+    assert rec["twosum_not_exact"] == 0
+    assert rec["fast2sum_ordered_not_exact"] == 0
+    assert rec["fast2sum_unordered_not_exact"] > 0
+    assert rec["ordered_pairs"] > finite * finite // 2 - finite
+    # overflow only near the top of the range: a small share of the pairs
+    assert 0 < rec["twosum_overflow"] < 1e-2 * rec["pairs"]
+    assert rec["sum_overflow"] <= rec["twosum_overflow"]
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_compensated_sums_exhaustive_slices(fmt):
+    """The same check re-run on slices of first operands (every second
+    operand): around 1, the subnormals, the largest values (overflow), and
+    negative numbers; the slices' counts are consistent with the record."""
+    one = 0x3C00 if fmt == "f16" else 0x3F80
+    top = 0x7BFF if fmt == "f16" else 0x7F7F
+    total = {k: 0 for k in oracle.EFT_COUNTS}
+    for lo, hi in [(one - 32, one + 32), (0, 48), (top - 16, top + 1),
+                   (0x8000 | one, (0x8000 | one) + 16)]:
+        c = oracle.eft_exhaustive(fmt, lo, hi)
+        assert c["twosum_not_exact"] == 0 and c["fast2sum_ordered_not_exact"] == 0
+        for k in total:
+            total[k] += c[k]
+    assert total["twosum_overflow"] > 0 and total["fast2sum_unordered_not_exact"] > 0
+    rec = json.load(open(EFT_GOLDEN))[fmt]
+    assert total["twosum_overflow"] <= rec["twosum_overflow"]
