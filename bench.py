@@ -71,16 +71,29 @@ def measured_traffic(tag: str):
     return None if v is None else v.get("hbm_bytes_per_launch")
 
 
+def window_drift(energy, steps, first, last):
+    """Relative energy drift max |E_n - E_first| / E_first over the samples
+    taken from step `first` to step `last`; None with fewer than two."""
+    sel = (steps >= first) & (steps <= last)
+    e = energy[sel]
+    if len(e) < 2:
+        return None
+    return float(np.max(np.abs(e - e[0])) / abs(e[0]))
+
+
 def run_variant(hw, torch, w, storage, comp, steps, warmup, tile):
     pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, w.order, storage, comp, w.dx,
-                    w.dt, 0, (warmup + steps) // ENERGY_EVERY + 4)
+                    w.dt, 0, (warmup + steps) // ENERGY_EVERY + 8)
     plan = hw.Plan(pb)
     plan.set_tile(tile)
     plan.set_material([w.rho, w.kappa])
     plan.set_fields(w.fields())
     stream = torch.cuda.current_stream()
-    plan.record_energy()
     plan.advance(warmup, ENERGY_EVERY)
+    # energy at the start and at the end of the timed window, recorded
+    # outside the events; inside, every ENERGY_EVERY steps
+    plan.record_energy()
+    start = plan.step
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -91,6 +104,8 @@ def run_variant(hw, torch, w, storage, comp, steps, warmup, tile):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
+    plan.record_energy()
+    end = plan.step
     # average duration of the step kernel alone: back-to-back launches with
     # no energy evaluation in between, bracketed by events on the same stream
     nk = min(200, max(steps, 1))
@@ -103,54 +118,129 @@ def run_variant(hw, torch, w, storage, comp, steps, warmup, tile):
     kernel_ms = k0.elapsed_time(k1) / nk
     energy, esteps = plan.energy_trace()
     plan.close()
-    drift = float(np.max(np.abs(energy - energy[0])) / energy[0])
     cells = w.nx * w.ny
     return {
         "glups": cells * steps / (ms * 1e-3) / 1e9,
         "ms_per_step": ms / steps,
         "wall_s": wall,
         "kernel_ms": kernel_ms,
-        "energy_drift": drift,
-        "energy_samples": int(len(energy)),
+        "energy_drift_window": window_drift(energy, esteps, start, end),
+        "energy_samples_window": int(np.sum((esteps >= start) & (esteps <= end))),
         "bytes_per_cell": bytes_per_cell(storage, comp),
         "hbm_gbs_algorithmic": bytes_per_cell(storage, comp) * cells / (kernel_ms * 1e-3) / 1e9,
     }
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The oracle (fp16 storage, fp32 stencil, TwoSum update, i.e. the same
-    arithmetic as the headline variant) on the same 4096^2 workload, from its
-    initial state, for as many whole steps as fit in about target_s."""
+LAYERED_GOLDEN = os.path.join(ROOT, "tests", "golden", "layered4096_fp64_energy.csv")
+
+
+def read_layered_golden(path=LAYERED_GOLDEN):
+    """The FP64 oracle's energy of the 4096^2 layered workload by rounded
+    start ('f16', 'f32', 'bf16') and step, or {} if it is missing."""
+    out = {}
+    if not os.path.exists(path):
+        return out
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        start, step, e = line.strip().split(",")
+        out.setdefault(start, {})[int(step)] = float(e)
+    return out
+
+
+def drift_run(hw, w, storage, comp, tile, nsteps, ref):
+    """The workload's full run (untimed): energy every ENERGY_EVERY steps,
+    compared with the FP64 oracle's energy from the same rounded start.  The
+    oracle conserves its energy to roundoff (pinned), so where its stored
+    record has no entry for a step its starting energy stands for it."""
+    pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, w.order, storage, comp, w.dx,
+                    w.dt, 0, nsteps // ENERGY_EVERY + 2)
+    plan = hw.Plan(pb)
+    plan.set_tile(tile)
+    plan.set_material([w.rho, w.kappa])
+    plan.set_fields(w.fields())
+    plan.advance(nsteps, ENERGY_EVERY)
+    energy, esteps = plan.energy_trace()
+    plan.close()
+    out = {"steps": nsteps, "energy_samples": int(len(energy)),
+           "energy_drift_self": float(np.max(np.abs(energy - energy[0])) / energy[0])}
+    if ref:
+        e_ref = np.array([ref.get(int(n), ref[0]) for n in esteps])
+        out["energy_drift_vs_fp64"] = float(np.max(np.abs(energy - e_ref)) / ref[0])
+        out["fp64_reference_steps"] = sorted(n for n in ref if n <= nsteps)
+    else:
+        out["energy_drift_vs_fp64"] = None
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, target_s=12.0):
+    """The FP64 oracle (fp64 storage and stencil, plain update: the
+    reference solver) on the same 4096^2 workload from its initial state,
+    with all of the oracle's threads and with one thread, each for about
+    target_s seconds of whole steps (a one-step call first sizes the run;
+    each call's set-up is included in its time)."""
     import oracle
-    f = {k: oracle.round_to(v, "f16") for k, v in w.fields().items()}
+    f0 = w.fields()
     args = (w.nx, w.ny, w.order, w.dx, w.dt, w.rho, w.kappa)
-    # a call pays a fixed set-up (coefficient tables) before its steps:
-    # after a warm-up call, calibrate the per-step cost from a 2-step and a
-    # 6-step call, then time one call sized to about target_s, set-up
-    # included
-    run = lambda n, f, c: oracle.acoustic2d(*args, f, storage="f16", stencil="f32",
-                                            comp="twosum", comps=c, nsteps=n)
-    f, c, _ = run(1, f, None)
-    t = time.perf_counter()
-    f, c, _ = run(2, f, c)
-    t2 = time.perf_counter() - t
-    t = time.perf_counter()
-    f, c, _ = run(6, f, c)
-    t6 = time.perf_counter() - t
-    per_step = max((t6 - t2) / 4, t6 / 12)
-    setup = max(t2 - 2 * per_step, 0.0)
-    steps = max(1, int((target_s - setup) / per_step))
-    t = time.perf_counter()
-    run(steps, f, c)
-    secs = time.perf_counter() - t
-    return {"value": w.nx * w.ny * steps / secs / 1e9, "unit": "GLUPS",
-            "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the {w.nx}x{w.ny} order-4 layered "
-                      f"workload, fp16+TwoSum emulated, {secs:.1f} s"}
+
+    def rate(threads):
+        t = time.perf_counter()
+        f, _, _ = oracle.acoustic2d(*args, f0, storage="f64", stencil="f64", comp="none",
+                                    nsteps=1, nthreads=threads)
+        t1 = time.perf_counter() - t
+        steps = max(1, int(target_s / t1))
+        t = time.perf_counter()
+        oracle.acoustic2d(*args, f, storage="f64", stencil="f64", comp="none",
+                          nsteps=steps, nthreads=threads)
+        secs = time.perf_counter() - t
+        return w.nx * w.ny * steps / secs / 1e9, steps, secs
+
+    nthreads = oracle.max_threads()
+    g_all, n_all, s_all = rate(0)
+    g_one, n_one, s_one = rate(1)
+    return {"value": g_all, "unit": "GLUPS", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n_all} steps of the {w.nx}x{w.ny} order-4 layered workload "
+                      f"({s_all:.1f} s, {nthreads} threads); one thread: {n_one} steps "
+                      f"({s_one:.1f} s)",
+            "arithmetic": "fp64 storage, fp64 stencil, plain update (the FP64 reference)",
+            "single_thread_value": g_one,
+            "nproc": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
 
 
 ELASTIC_BYTES_ALGO = {"f32+none": 84, "f16+twosum": 84, "f16+none": 48}
 ELASTIC_BYTES_TWO_PASS = {"f32+none": 120, "f16+twosum": 120, "f16+none": 60}
+
+
+def elastic_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("elastic3d.hip", "hw_device.h", "hw_internal.h"):
+        with open(os.path.join(ROOT, "paper_2310_00236_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic3d(tag: str):
+    """HBM bytes per launch of the 3D step kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current source."""
+    path = os.path.join(ROOT, "profiles", "traffic_elastic3d_512.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != elastic_source_digest():
+        return None
+    v = rec.get("variants", {}).get(tag)
+    return None if v is None else v.get("hbm_bytes_per_launch")
 
 
 def run_elastic(hw, torch, n, steps, warmup, variants):
@@ -162,12 +252,14 @@ def run_elastic(hw, torch, n, steps, warmup, variants):
     w = workloads.smooth3d(n, nsteps=steps)
     every = max(steps // 10, 1)
     out = {}
+    shapes = hw.tiles("elastic3d")
     for storage, comp in variants:
         key = f"{storage}+{comp}"
         pb = hw.Problem("elastic3d", n, n, n, 2, storage, comp, w.dx, w.dt, 0,
-                        (steps + warmup) // every + 4)
+                        (steps + warmup) // every + 8)
         plan = hw.Plan(pb)
-        plan.set_tile(tuning.best_tile("elastic3d", 2, storage, comp, n, n, n))
+        tile = tuning.best_tile("elastic3d", 2, storage, comp, n, n, n)
+        plan.set_tile(tile)
         plan.set_material([w.rho, w.lam, w.mu])
         plan.set_fields(w.fields())
         stream = torch.cuda.current_stream()
@@ -181,6 +273,16 @@ def run_elastic(hw, torch, n, steps, warmup, variants):
         t1.record(stream)
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1)
+        plan.record_energy()
+        # the step kernel alone: back-to-back launches, no energy in between
+        nk = 20
+        k0 = torch.cuda.Event(enable_timing=True)
+        k1 = torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        plan.advance(nk, 0)
+        k1.record(stream)
+        torch.cuda.synchronize()
+        kernel_ms = k0.elapsed_time(k1) / nk
         energy, _ = plan.energy_trace()
         plan.close()
         cells = n ** 3
@@ -188,18 +290,31 @@ def run_elastic(hw, torch, n, steps, warmup, variants):
         out[key] = {
             "glups": cells * steps / (ms * 1e-3) / 1e9,
             "ms_per_step": step_ms,
+            "kernel_ms": kernel_ms,
+            "tile": hw.tile_label(shapes[tile]),
             "energy_drift": float(np.max(np.abs(energy - energy[0])) / energy[0]),
+            "energy_samples": int(len(energy)),
             "bytes_per_cell_step_algorithmic": ELASTIC_BYTES_ALGO[key],
-            "bytes_per_cell_step_two_pass": ELASTIC_BYTES_TWO_PASS[key],
-            "hbm_gbs_algorithmic": ELASTIC_BYTES_ALGO[key] * cells / (step_ms * 1e-3) / 1e9,
-            "hbm_gbs_two_pass": ELASTIC_BYTES_TWO_PASS[key] * cells / (step_ms * 1e-3) / 1e9,
+            "hbm_gbs_algorithmic": ELASTIC_BYTES_ALGO[key] * cells / (kernel_ms * 1e-3) / 1e9,
+            "frac_hbm": ELASTIC_BYTES_ALGO[key] * cells / (kernel_ms * 1e-3) / 1e9
+            / PEAK_HBM_GBS,
         }
         print(f"# elastic3d {n}^3 {key}: {out[key]}", file=sys.stderr, flush=True)
-    return {"workload": f"elastic3d order-2 {n}^3 periodic, smooth random medium, "
-                        f"CFL 0.3, explosive source, {steps} steps",
-            "variants": out,
-            "vs_f32": out["f16+twosum"]["glups"] / out["f32+none"]["glups"]
-            if "f16+twosum" in out and "f32+none" in out else None}
+    res = {"workload": f"elastic3d order-2 {n}^3 periodic, smooth random medium, "
+                       f"CFL 0.3, explosive source, {steps} steps",
+           "variants": out,
+           "vs_f32": out["f16+twosum"]["glups"] / out["f32+none"]["glups"]
+           if "f16+twosum" in out and "f32+none" in out else None}
+    head = "f16+twosum" if "f16+twosum" in out else next(iter(out))
+    h = out[head]
+    res["roofline"] = {
+        "bound": "hbm", "achieved": h["hbm_gbs_algorithmic"], "peak": PEAK_HBM_GBS,
+        "unit": "GB/s", "frac": h["frac_hbm"],
+        "traffic": measured_traffic3d(head) if n == 512 else None,
+        "kernel": "el3d_fused1_kernel", "variant": head,
+        "bytes_per_cell_step": ELASTIC_BYTES_ALGO[head], "cells_per_launch": n ** 3,
+        "kernel_ms": h["kernel_ms"]}
+    return res
 
 
 def run_batched(hw, torch, nshots):
@@ -493,43 +608,63 @@ def run_app_a(hw, torch, nsteps=60000, big=4096, big_steps=400):
     return res
 
 
-def run_serving(hw, torch, nreq, glups2d, glups3d, chunk=200):
+def run_serving(hw, torch, nreq, glups, budget=None, chunk=200, seed=None):
     """Poisson stream of mixed requests (70% 2D order-4 512^2..4096^2, 30% 3D
     128^3..384^3, 1000..10000 steps, fp32 or fp16+TwoSum), arrival rate set so
-    that the offered work is about 80% of the measured throughput; admission
-    by device footprint; continuous batching in chunks of `chunk` steps."""
+    that the offered work is about 80% of the measured solo throughput;
+    admission by device footprint (budget: 80% of free HBM unless given);
+    continuous batching in chunks of `chunk` steps, each kernel group on its
+    own stream.  A request's inputs are drawn when it is admitted.
+    glups: solo rates by (kind, precision)."""
     import workloads
     from paper_2310_00236_amd import serve
-    probe = workloads.request_stream(nreq, rate=1.0)
-    work = []
-    for r in probe:
-        cells = r.size ** 2 if r.kind == "acoustic2d" else r.size ** 3
-        work.append(cells * r.nsteps / ((glups2d if r.kind == "acoustic2d" else glups3d) * 1e9))
-    rate = 0.8 / (sum(work) / len(work))
-    reqs = workloads.request_stream(nreq, rate=rate)
-    jobs = []
-    t = time.perf_counter()
-    for r in reqs:
-        w = workloads.request_problem(r)
+
+    def solo(r):
+        return glups[(r.kind, r.precision)] * 1e9
+
+    def cells(r):
+        return r.size ** 2 if r.kind == "acoustic2d" else r.size ** 3
+
+    probe = workloads.request_stream(nreq, rate=1.0, seed=seed)
+    mean_work = sum(cells(r) * r.nsteps / solo(r) for r in probe) / len(probe)
+    rate = 0.8 / mean_work
+    reqs = workloads.request_stream(nreq, rate=rate, seed=seed)
+
+    def problem(r, dt=1.0, dx=1.0):
         storage, comp = ("f32", "none") if r.precision == "f32" else ("f16", "twosum")
         if r.kind == "acoustic2d":
-            pb = hw.Problem("acoustic2d", w.nx, w.ny, 1, 4, storage, comp, w.dx, w.dt, 0, 0)
-            mat = [w.rho, w.kappa]
-        else:
-            pb = hw.Problem("elastic3d", w.nx, w.ny, w.nz, 2, storage, comp, w.dx, w.dt, 0, 0)
-            mat = [w.rho, w.lam, w.mu]
+            return hw.Problem("acoustic2d", r.size, r.size, 1, 4, storage, comp, dx, dt, 0, 0)
+        return hw.Problem("elastic3d", r.size, r.size, r.size, 2, storage, comp, dx, dt, 0, 0)
+
+    def inputs(r):
+        w = workloads.request_problem(r)
+        mat = [w.rho, w.kappa] if r.kind == "acoustic2d" else [w.rho, w.lam, w.mu]
+        return problem(r, w.dt, w.dx), mat, w.fields()
+
+    jobs = []
+    for r in reqs:
+        pb = problem(r)               # the footprint does not depend on dt
         jobs.append(serve.Job(id=r.index, arrival=r.arrival, footprint=hw.footprint(pb),
-                              nsteps=r.nsteps, cells=pb.cells, payload=(pb, mat, w.fields())))
-    gen_s = time.perf_counter() - t
-    free, _ = torch.cuda.mem_get_info()
-    budget = int(0.8 * free)
-    summary, done = serve.serve(jobs, budget, chunk_steps=chunk)
+                              nsteps=r.nsteps, cells=pb.cells,
+                              payload=(lambda r=r: inputs(r))))
+    if budget is None:
+        free, _ = torch.cuda.mem_get_info()
+        budget = int(0.8 * free)
+    def note(j):
+        print(f"# served request {j.id} ({len(jobs)} in the stream): latency "
+              f"{j.latency:.2f} s", file=sys.stderr, flush=True)
+
+    summary, done = serve.serve(jobs, budget, chunk_steps=chunk, on_retire=note)
+    # the fraction of the wall time the GPU would need to run the served work
+    # one request at a time at the solo rates
+    busy = sum(cells(r) * r.nsteps / solo(r) for r in reqs
+               if any(j.id == r.index for j in done))
     summary.update({"requests": nreq, "arrival_rate_per_s": rate,
                     "hbm_budget_bytes": budget, "chunk_steps": chunk,
-                    "input_generation_s": gen_s,
+                    "utilisation_at_solo_rates": busy / summary["wall_s"],
                     "workload": "Poisson stream, 70% 2D order-4 512^2-4096^2 / 30% 3D "
                                 "128^3-384^3, 1000-10000 steps, fp32 or fp16+TwoSum"})
-    print(f"# serving: {summary}", file=sys.stderr, flush=True)
+    print(f"# serving (budget {budget / 1e9:.1f} GB): {summary}", file=sys.stderr, flush=True)
     return summary
 
 
@@ -548,7 +683,13 @@ def main():
     ap.add_argument("--elastic-n", type=int, default=512)
     ap.add_argument("--elastic-steps", type=int, default=2000)
     ap.add_argument("--shots", type=int, default=64)
-    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--requests", type=int, default=120,
+                    help="requests of the serving stream (80%% of free HBM as budget)")
+    ap.add_argument("--small-budget-requests", type=int, default=40,
+                    help="requests of the second serving stream, under an 8 GB budget")
+    ap.add_argument("--drift-steps", type=int, default=10000,
+                    help="length of each variant's untimed full run, for the energy "
+                         "drift against the FP64 oracle (0: skip)")
     ap.add_argument("--sections", default="2d,3d,batched,serving,paper,app_a",
                     help="comma list of workloads to run: 2d (always reported), "
                          "3d, batched, serving, paper (the Sec. 3 experiment), "
@@ -600,7 +741,16 @@ def main():
     head_key = "f16+twosum" if "f16+twosum" in results else next(iter(results))
     head = results[head_key]
     cells = w.nx * w.ny
+    # the full run of every variant (untimed), energy against the FP64 oracle
+    if args.drift_steps > 0:
+        gold = read_layered_golden() if (w.nx, w.ny) == (4096, 4096) else {}
+        for key, r in results.items():
+            storage, comp = key.split("+")
+            r["full_run"] = drift_run(hw, w, storage, comp, tiles[key], args.drift_steps,
+                                      gold.get(storage))
+            print(f"# {key} full run: {r['full_run']}", file=sys.stderr, flush=True)
     traffic = measured_traffic(head_key)
+    shape = hw.tiles("acoustic2d")[tiles[head_key]]
     roofline = {
         "bound": "hbm",
         "achieved": head["hbm_gbs_algorithmic"],
@@ -608,7 +758,8 @@ def main():
         "unit": "GB/s",
         "frac": head["hbm_gbs_algorithmic"] / PEAK_HBM_GBS,
         "traffic": traffic,
-        "kernel": "ac2d_step_kernel",
+        "kernel": "ac2d_march1_kernel" if shape[3] == 1 else "ac2d_step1_kernel",
+        "tile": hw.tile_label(shape),
         "bytes_per_cell_step": head["bytes_per_cell"],
         "cells_per_launch": cells,
         "kernel_ms": head["kernel_ms"],
@@ -622,8 +773,15 @@ def main():
     if "batched" in sections:
         extra["batched"] = run_batched(hw, torch, args.shots)
     if "serving" in sections:
-        g3 = extra["elastic3d"]["variants"]["f16+twosum"]["glups"]
-        extra["serving"] = run_serving(hw, torch, args.requests, head["glups"], g3)
+        e3 = extra["elastic3d"]["variants"]
+        solo = {("acoustic2d", "f16+comp"): results.get("f16+twosum", head)["glups"],
+                ("acoustic2d", "f32"): results.get("f32+none", head)["glups"],
+                ("elastic3d", "f16+comp"): e3["f16+twosum"]["glups"],
+                ("elastic3d", "f32"): e3["f32+none"]["glups"]}
+        extra["serving"] = run_serving(hw, torch, args.requests, solo)
+        if args.small_budget_requests > 0:
+            extra["serving_8GB"] = run_serving(hw, torch, args.small_budget_requests, solo,
+                                               budget=8 * 10 ** 9, seed=workloads.seed_for(5, 9999))
     if "paper" in sections:
         extra["paper2d"] = run_paper(hw, torch, args.paper_steps)
     if "app_a" in sections:
@@ -647,9 +805,15 @@ def main():
                                f"{args.steps} steps",
                    "variant": head_key, "tile": list(hw.tiles("acoustic2d")[tiles[head_key]]),
                    "energy_every": ENERGY_EVERY},
-        "energy_drift": head["energy_drift"],
+        "energy_drift": head["energy_drift_window"],
+        "energy_drift_vs_fp64": head.get("full_run", {}).get("energy_drift_vs_fp64"),
+        "energy_drift_steps": head.get("full_run", {}).get("steps"),
         "vs_f32": (head["glups"] / f32["glups"]) if f32 else None,
-        "variants": {k: {"glups": v["glups"], "energy_drift": v["energy_drift"],
+        "variants": {k: {"glups": v["glups"], "ms_per_step": v["ms_per_step"],
+                         "energy_drift_window": v["energy_drift_window"],
+                         "energy_drift_vs_fp64": v.get("full_run", {}).get(
+                             "energy_drift_vs_fp64"),
+                         "full_run": v.get("full_run"),
                          "kernel_ms": v["kernel_ms"],
                          "hbm_gbs_algorithmic": v["hbm_gbs_algorithmic"],
                          "frac_hbm": v["hbm_gbs_algorithmic"] / PEAK_HBM_GBS,
