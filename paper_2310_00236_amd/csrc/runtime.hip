@@ -1313,6 +1313,9 @@ hw_status hw_plan_set_tile(hw_plan *p, int32_t tile)
         return fail(HW_E_INVAL, "plan is NULL");
     if (tile < 0 || tile >= num_tiles(p->pb))
         return fail(HW_E_INVAL, "tile index out of range");
+    if (p->pb.comp == HW_COMP_TWOSUM8 && kTiles2D[tile].kind == 1)
+        return fail(HW_E_INVAL, "8-bit compensation words run on the tile kernels "
+                                "(kinds 0 and 3), not on the marching kind 1");
     p->tile = tile;
     return HW_OK;
 }

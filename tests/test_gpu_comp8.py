@@ -55,10 +55,35 @@ def test_bitexact(storage, order):
     assert any(np.any(wc[k] != 0) for k in wc)          # the words are in use
 
 
+TILE_KINDS = [t for t, s in enumerate(hw.tiles("acoustic2d")) if s[3] != 1]
+MARCH_KINDS = [t for t, s in enumerate(hw.tiles("acoustic2d")) if s[3] == 1]
+
+
+def test_march_shapes_are_refused():
+    """8-bit words run on the tile kernels only: a marching shape is refused
+    by hw_plan_set_tile, and a batch given one runs the group on shape 0."""
+    nx, ny = 65, 17
+    rho, kappa, dt, f = _case(nx, ny, 4, "f16", 811)
+    pb = hw.Problem("acoustic2d", nx, ny, 1, 4, "f16", "twosum8", 1.0, dt, 0, 0)
+    p = hw.Plan(pb)
+    for t in MARCH_KINDS:
+        with pytest.raises(hw.HalfwaveError) as e:
+            p.set_tile(t)
+        assert e.value.name == "HW_E_INVAL"
+    p.set_material([rho, kappa])
+    p.set_fields(f)
+    hw.batch_advance([p], [40], tile=MARCH_KINDS[0])
+    g, gc = p.get_fields(comps=True)
+    p.close()
+    w, wc, _ = _oracle(nx, ny, 4, "f16", dt, rho, kappa, f, 40)
+    assert_bitexact(g, w, "batch with a march shape")
+    assert_bitexact(gc, wc, "batch with a march shape, comps")
+
+
 @pytest.mark.parametrize("shape", [(1, 1), (5, 7), (65, 17), (257, 3), (3, 130)])
-@pytest.mark.parametrize("tile", range(len(hw.tiles("acoustic2d"))))
+@pytest.mark.parametrize("tile", TILE_KINDS)
 def test_sizes_and_tiles(shape, tile):
-    """Every tile setting (march shapes run on tile 0 with 8-bit words)."""
+    """Every tile shape the 8-bit words run on."""
     nx, ny = shape
     rho, kappa, dt, f = _case(nx, ny, 4, "f16", 811)
     p = _plan(nx, ny, 4, "f16", dt, rho, kappa, f, tile=tile)
