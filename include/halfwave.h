@@ -276,7 +276,11 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  * a plane per workgroup; tz planes per workgroup; kind:
  *   acoustic2d  0 = one tile per workgroup (4 wavefronts), 3 = the same
  *               with 8 wavefronts, 1 = a workgroup marches down a strip ty
- *               rows tall;
+ *               rows tall; 4 and 5 = two time steps per launch (4 and 8
+ *               wavefronts; tz = 2): a workgroup advances its tile by two
+ *               steps in one pass over memory, recomputing the cells around
+ *               it that the second step needs (an odd step left over runs
+ *               on shape 0);
  *   elastic3d   0 = two passes per step (velocities, then stresses), one
  *               plane per workgroup; 2 = one fused pass per step, a
  *               workgroup walks a tx by ty column through tz planes;
@@ -286,8 +290,8 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  *               workgroup.
  * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
  * results.  Plans with HW_COMP_TWOSUM8 take kinds 0 and 3 only (HW_E_INVAL
- * for kind 1); in hw_batch_advance a kind-1 tile argument runs their group
- * on shape 0.  Any of the output pointers may be NULL. */
+ * for the others); in hw_batch_advance another tile argument runs their
+ * group on shape 0.  Any of the output pointers may be NULL. */
 int32_t hw_tile_count(int32_t physics);
 hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx,
                        int32_t *ty, int32_t *tz, int32_t *kind);

@@ -19,8 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhalfwave.so")
-SOURCES = ["acoustic2d.hip", "acoustic2d_var.hip", "elastic3d.hip", "elastic2d.hip", "runtime.hip",
-           "convert.hip"]
+SOURCES = ["acoustic2d.hip", "acoustic2d_var.hip", "acoustic2d_tb.hip", "elastic3d.hip",
+           "elastic2d.hip", "runtime.hip", "convert.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -38,7 +38,7 @@ def _obj(src: str, outdir: str) -> str:
     return os.path.join(outdir, os.path.splitext(src)[0] + ".o")
 
 
-def build(verbose: bool = False, jobs: int = 5) -> str:
+def build(verbose: bool = False, jobs: int = 7) -> str:
     """Compile every HIP source for gfx950 and link libhalfwave.so."""
     outdir = os.path.join(HERE, "_build")
     os.makedirs(outdir, exist_ok=True)

@@ -159,8 +159,9 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
                 hipLaunchKernelGGL((ac2d_step_kernel<S, COMP, ORDER, V, T,        \
                                                      false, 0, 8>),               \
                                    grid, block8, 0, s, a);                        \
-        } else if constexpr (COMP == COMP_TWOSUM8) {                              \
-            return hipErrorInvalidValue;   /* 8-bit words: tile kernels only */   \
+        } else if constexpr (COMP == COMP_TWOSUM8 ||                              \
+                             steps_per_launch2d(kTiles2D[n]) != 1) {              \
+            return hipErrorInvalidValue;   /* not a one-step shape here */        \
         } else {                                                                  \
             if (one)                                                              \
                 hipLaunchKernelGGL((ac2d_march1_kernel<S, COMP, ORDER, V, T>),    \
@@ -175,9 +176,9 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
         HW_TILE(7) HW_TILE(8)
 #undef HW_TILE
     default:
-        return hipErrorInvalidValue;
+        return hipErrorInvalidValue;   // two-step shapes: launch_ac2d_step2
     }
-    static_assert(kNumTiles2D == 9, "update the tile dispatch");
+    static_assert(kNumTiles2D == 11, "update the tile dispatch");
     return hipGetLastError();
 }
 

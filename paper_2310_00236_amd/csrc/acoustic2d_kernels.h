@@ -306,7 +306,10 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     constexpr int KY = cdiv(TY + R - 1 + OB, NW);   // vy rows [-R, TY+R-1)
     constexpr int KC = TY / NW;                // the tile's own rows
     static_assert(TY % NW == 0, "tile height must be a multiple of the wavefront count");
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    // the wavefront index in a scalar register: row tests become scalar
+    // branches and row offsets scalar arithmetic
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ln = threadIdx.x & 63;
     const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
     using A = Sten<S, SP>;
     using AT = typename A::T;

@@ -107,6 +107,11 @@ struct El3dOne {
 //   2D kind 1: a workgroup marches down a strip tx wide and ty rows tall;
 //   2D kind 3: as kind 0 with 8 wavefronts (two rows of the tile per
 //              wavefront fewer; faster for bf16 and fp32);
+//   2D kind 4: two time steps per launch (temporal blocking): a workgroup
+//              of 4 wavefronts advances its tx by ty tile from step n to
+//              n+2, recomputing the cells around it the second step needs
+//              (tz holds the steps per launch); kind 5: the same with 8
+//              wavefronts;
 //   3D kind 0: two passes (velocities, then stresses), one tx by ty tile of
 //              one z plane per workgroup;
 //   3D kind 2: one fused pass, a workgroup walks a tx by ty column through
@@ -116,7 +121,13 @@ struct TileShape { int tx, ty, kind, tz; };
 // 2D: the width is 64 lanes times 1, 2 or 4 cells per lane
 constexpr TileShape kTiles2D[] = {{64, 16, 0, 1}, {64, 32, 0, 1}, {128, 16, 0, 1},
                                   {64, 64, 1, 1}, {64, 128, 1, 1}, {128, 64, 1, 1},
-                                  {128, 128, 1, 1}, {64, 16, 3, 1}, {128, 16, 3, 1}};
+                                  {128, 128, 1, 1}, {64, 16, 3, 1}, {128, 16, 3, 1},
+                                  {64, 16, 4, 2}, {64, 32, 5, 2}};
+// Time steps one launch of a 2D shape advances.
+constexpr int steps_per_launch2d(const TileShape &t)
+{
+    return t.kind == 4 || t.kind == 5 ? 2 : 1;
+}
 constexpr TileShape kTiles3D[] = {{64, 4, 0, 1},    {256, 1, 0, 1},   {64, 6, 2, 128},
                                   {64, 6, 2, 64},   {64, 6, 2, 512},  {64, 10, 2, 128},
                                   {64, 14, 2, 128}};
@@ -141,6 +152,10 @@ hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage
 hipError_t launch_ac2d_variant(const Ac2dBatch &a, const Ac2dDesc *one, int format,
                                int comp, int order, int tile, int stencil,
                                hipStream_t s);
+// Two steps per launch (tile shapes of kind 4 and 5; no 8-bit compensation
+// words, no source, receivers or stencil variants).
+hipError_t launch_ac2d_step2(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
+                             int comp, int order, int tile, hipStream_t s);
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
                               int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);

@@ -314,15 +314,48 @@ void tile_counts(const hw_plan *p, int tile, int32_t *tx, int32_t *ty, int32_t *
 }
 
 // Steps launched between host interventions are captured into a HIP graph
-// in runs of this many (even, so every shot's field set returns to where the
-// run started).
+// in runs of this many (a multiple of 4: an even number of launches of one
+// or two steps, so every shot's field set returns to where the run started).
 constexpr int kGraphSteps = 32;
+static_assert(kGraphSteps % 4 == 0, "graph runs of an even number of launches");
 
-// Launch one time step for a group of plans sharing a kernel, in launches of
-// at most kMaxBatch shots; parity[i] is plan i's current field set.  Host
-// state is not touched (the same launches can be recorded into a graph).
+// The shape a group of plans sharing a kernel runs on when given `tile`:
+// acoustic plans with a point source or receivers, a non-default stencil or
+// 8-bit compensation words run on the one-step tile kernels -- shape 0,
+// except that 8-bit words keep a kind-3 shape -- and `single` asks for a
+// one-step shape (shape 0 in place of a two-step one).
+int group_tile(hw_plan *const *plans, int n, int tile, bool single)
+{
+    const hw_plan *p0 = plans[0];
+    if (p0->pb.physics != HW_ACOUSTIC2D)
+        return tile;
+    bool forced = false;
+    for (int i = 0; i < n; ++i)
+        forced = forced || plans[i]->counts();
+    const int kind = kTiles2D[tile].kind;
+    if (forced || p0->pb.stencil != HW_STENCIL_F32)
+        return 0;
+    if (p0->pb.comp == HW_COMP_TWOSUM8 && kind != 0 && kind != 3)
+        return 0;
+    if (single && steps_per_launch2d(kTiles2D[tile]) != 1)
+        return 0;
+    return tile;
+}
+
+// Time steps one launch of the group advances on `tile`.
+int group_steps(hw_plan *const *plans, int n, int tile)
+{
+    if (plans[0]->pb.physics != HW_ACOUSTIC2D)
+        return 1;
+    return steps_per_launch2d(kTiles2D[group_tile(plans, n, tile, false)]);
+}
+
+// Launch one launch's worth of time steps (group_steps, or one step if
+// `single`) for a group of plans sharing a kernel, in launches of at most
+// kMaxBatch shots; parity[i] is plan i's current field set.  Host state is
+// not touched (the same launches can be recorded into a graph).
 hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
-                           const int *parity, hipStream_t s)
+                           const int *parity, hipStream_t s, bool single = false)
 {
     const hw_plan *p0 = plans[0];
     if (p0->pb.physics == HW_ELASTIC2D) {
@@ -358,16 +391,11 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             Ac2dBatch a;
             std::memset(&a, 0, sizeof(a));
             a.nshots = m;
-            // plans with a point source or receivers run on tile shape 0
             bool forced = false;
             for (int i = 0; i < m; ++i)
                 forced = forced || plans[base + i]->counts();
             const int stencil = p0->pb.stencil;
-            // variants and 8-bit compensation words run on tile kernels
-            const bool tile_only = forced || stencil != HW_STENCIL_F32 ||
-                                   (p0->pb.comp == HW_COMP_TWOSUM8 &&
-                                    kTiles2D[tile].kind == 1);
-            const int t = tile_only ? 0 : tile;
+            const int t = group_tile(plans + base, m, tile, single);
             int64_t total = 0;
             for (int i = 0; i < m; ++i) {
                 hw_plan *p = plans[base + i];
@@ -384,9 +412,13 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
                 return fail(HW_E_INVAL, "batch has too many tiles for one launch");
             a.tile_start[m] = (int32_t)total;
             a.total_tiles = (int32_t)total;
-            e = launch_ac2d_step(a, m == 1 ? &plans[base]->h2 : nullptr,
-                                 p0->pb.storage, p0->pb.comp, p0->pb.order, t, forced,
-                                 stencil, s);
+            if (steps_per_launch2d(kTiles2D[t]) == 2)
+                e = launch_ac2d_step2(a, m == 1 ? &plans[base]->h2 : nullptr,
+                                      p0->pb.storage, p0->pb.comp, p0->pb.order, t, s);
+            else
+                e = launch_ac2d_step(a, m == 1 ? &plans[base]->h2 : nullptr,
+                                     p0->pb.storage, p0->pb.comp, p0->pb.order, t,
+                                     forced, stencil, s);
             // plans with a source or receivers count their steps on the device
             StepCounters c;
             c.n = 0;
@@ -424,37 +456,41 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
     return HW_OK;
 }
 
-void advance_state(hw_plan *const *plans, int n, int64_t steps)
+// Every launch reads one field set and writes the other.
+void advance_state(hw_plan *const *plans, int n, int64_t steps, int64_t launches)
 {
     for (int i = 0; i < n; ++i) {
         hw_plan *p = plans[i];
-        p->cur ^= (int)(steps & 1);
+        p->cur ^= (int)(launches & 1);
         p->step += steps;
     }
 }
 
-hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s)
+hw_status launch_group(hw_plan *const *plans, int n, int tile, hipStream_t s,
+                       bool single = false)
 {
     std::vector<int> par(n);
     for (int i = 0; i < n; ++i)
         par[i] = plans[i]->cur;
-    hw_status st = launch_group_raw(plans, n, tile, par.data(), s);
+    hw_status st = launch_group_raw(plans, n, tile, par.data(), s, single);
     if (st == HW_OK)
-        advance_state(plans, n, 1);
+        advance_state(plans, n, single ? 1 : group_steps(plans, n, tile), 1);
     return st;
 }
 
 // Record kGraphSteps steps of one group (starting from the plans' current
-// field sets) into an executable graph, via a capture stream.
+// field sets) into an executable graph, via a capture stream: an even number
+// of launches, so every plan's field set returns to where the run started.
 hw_status capture_run(hw_plan *const *plans, int n, int tile, hipStream_t cap,
                       hipGraphExec_t *out)
 {
     std::vector<int> par(n);
     for (int i = 0; i < n; ++i)
         par[i] = plans[i]->cur;
+    const int launches = kGraphSteps / group_steps(plans, n, tile);
     HW_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     hw_status st = HW_OK;
-    for (int g = 0; g < kGraphSteps && st == HW_OK; ++g) {
+    for (int g = 0; g < launches && st == HW_OK; ++g) {
         st = launch_group_raw(plans, n, tile, par.data(), cap);
         for (int i = 0; i < n; ++i)
             par[i] ^= 1;
@@ -531,10 +567,12 @@ hw_status run_steps(hw_plan *const *plans, int n, int tile, int64_t steps,
     bool direct = false;
     for (int i = 0; i < n; ++i)
         direct = direct || plans[i]->direct;
+    const int per = group_steps(plans, n, tile);      // steps per launch
+    const int64_t graph_launches = kGraphSteps / per;
     if (!direct && steps >= kGraphSteps + 1 && n == 1) {
         hw_plan *p = plans[0];
         if (p->cur != 0) {                 // align to the captured field set
-            if ((st = launch_group(plans, 1, tile, s)) != HW_OK)
+            if ((st = launch_group(plans, 1, tile, s, true)) != HW_OK)
                 return st;
             steps -= 1;
         }
@@ -550,7 +588,7 @@ hw_status run_steps(hw_plan *const *plans, int n, int tile, int64_t steps,
         }
         for (; steps >= kGraphSteps; steps -= kGraphSteps) {
             HW_HIP(hipGraphLaunch(p->graph, s));
-            advance_state(plans, 1, kGraphSteps);
+            advance_state(plans, 1, kGraphSteps, graph_launches);
         }
     } else if (!direct && steps >= 2 * kGraphSteps) {
         hipGraphExec_t exec = nullptr;
@@ -564,13 +602,16 @@ hw_status run_steps(hw_plan *const *plans, int n, int tile, int64_t steps,
                 (void)retire_graph(exec, s);
                 return fail(HW_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
             }
-            advance_state(plans, n, kGraphSteps);
+            advance_state(plans, n, kGraphSteps, graph_launches);
         }
         if ((st = retire_graph(exec, s)) != HW_OK)
             return st;
     }
-    for (; steps > 0; --steps)
+    for (; steps >= per; steps -= per)
         if ((st = launch_group(plans, n, tile, s)) != HW_OK)
+            return st;
+    for (; steps > 0; --steps)             // a last single step of a two-step shape
+        if ((st = launch_group(plans, n, tile, s, true)) != HW_OK)
             return st;
     return HW_OK;
 }
@@ -1313,9 +1354,10 @@ hw_status hw_plan_set_tile(hw_plan *p, int32_t tile)
         return fail(HW_E_INVAL, "plan is NULL");
     if (tile < 0 || tile >= num_tiles(p->pb))
         return fail(HW_E_INVAL, "tile index out of range");
-    if (p->pb.comp == HW_COMP_TWOSUM8 && kTiles2D[tile].kind == 1)
-        return fail(HW_E_INVAL, "8-bit compensation words run on the tile kernels "
-                                "(kinds 0 and 3), not on the marching kind 1");
+    if (p->pb.physics == HW_ACOUSTIC2D && p->pb.comp == HW_COMP_TWOSUM8 &&
+        kTiles2D[tile].kind != 0 && kTiles2D[tile].kind != 3)
+        return fail(HW_E_INVAL, "8-bit compensation words run on the one-step tile "
+                                "kernels (kinds 0 and 3) only");
     p->tile = tile;
     return HW_OK;
 }

@@ -48,9 +48,12 @@ def test_cfl_bounds():
 def test_tiles_listed():
     t2, t3 = hw.tiles("acoustic2d"), hw.tiles("elastic3d")
     assert len(t2) >= 2 and len(t3) >= 2
-    assert all(tx % 64 == 0 and ty % 4 == 0 and tz == 1 and kind in (0, 1, 3)
+    assert all(tx % 64 == 0 and ty % 4 == 0 and kind in (0, 1, 3, 4, 5)
                for tx, ty, tz, kind in t2)
-    assert all(ty % 8 == 0 for tx, ty, tz, kind in t2 if kind == 3)
+    # tz: time steps per launch (2 for the temporally blocked kinds 4 and 5)
+    assert all(tz == (2 if kind in (4, 5) else 1) for tx, ty, tz, kind in t2)
+    assert all(ty % 8 == 0 for tx, ty, tz, kind in t2 if kind in (3, 5))
+    assert any(kind == 4 for *_, kind in t2) and any(kind == 5 for *_, kind in t2)
     assert all((kind == 0 and tx * ty == 256 and tz == 1) or
                (kind == 2 and tx == 64 and (ty + 2) % 4 == 0 and tz >= 1)
                for tx, ty, tz, kind in t3)
