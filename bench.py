@@ -51,7 +51,8 @@ VARIANTS = [("f16", "twosum"), ("f32", "none"), ("f16", "none"), ("bf16", "none"
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for name in ("acoustic2d.hip", "acoustic2d_kernels.h", "hw_device.h", "hw_internal.h"):
+    for name in ("acoustic2d.hip", "acoustic2d_tb.hip", "acoustic2d_kernels.h", "hw_device.h",
+                 "hw_internal.h"):
         with open(os.path.join(ROOT, "paper_2310_00236_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -79,6 +80,12 @@ def window_drift(energy, steps, first, last):
     if len(e) < 2:
         return None
     return float(np.max(np.abs(e - e[0])) / abs(e[0]))
+
+
+def steps_per_launch(hw, tile) -> int:
+    """Time steps one launch of 2D tile shape `tile` advances (the
+    temporally blocked kinds 4 and 5 advance two)."""
+    return 2 if hw.tiles("acoustic2d")[tile][3] in (4, 5) else 1
 
 
 def run_variant(hw, torch, w, storage, comp, steps, warmup, tile):
@@ -119,15 +126,20 @@ def run_variant(hw, torch, w, storage, comp, steps, warmup, tile):
     energy, esteps = plan.energy_trace()
     plan.close()
     cells = w.nx * w.ny
+    per = steps_per_launch(hw, tile)
+    # a launch reads and writes the state once: per step, its bytes divided
+    # by the steps it advances
+    bpc = bytes_per_cell(storage, comp) / per
     return {
         "glups": cells * steps / (ms * 1e-3) / 1e9,
         "ms_per_step": ms / steps,
         "wall_s": wall,
         "kernel_ms": kernel_ms,
+        "steps_per_launch": per,
         "energy_drift_window": window_drift(energy, esteps, start, end),
         "energy_samples_window": int(np.sum((esteps >= start) & (esteps <= end))),
-        "bytes_per_cell": bytes_per_cell(storage, comp),
-        "hbm_gbs_algorithmic": bytes_per_cell(storage, comp) * cells / (kernel_ms * 1e-3) / 1e9,
+        "bytes_per_cell": bpc,
+        "hbm_gbs_algorithmic": bpc * cells / (kernel_ms * 1e-3) / 1e9,
     }
 
 
@@ -751,6 +763,8 @@ def main():
             print(f"# {key} full run: {r['full_run']}", file=sys.stderr, flush=True)
     traffic = measured_traffic(head_key)
     shape = hw.tiles("acoustic2d")[tiles[head_key]]
+    per = head["steps_per_launch"]
+    storage, comp = head_key.split("+")
     roofline = {
         "bound": "hbm",
         "achieved": head["hbm_gbs_algorithmic"],
@@ -758,11 +772,20 @@ def main():
         "unit": "GB/s",
         "frac": head["hbm_gbs_algorithmic"] / PEAK_HBM_GBS,
         "traffic": traffic,
-        "kernel": "ac2d_march1_kernel" if shape[3] == 1 else "ac2d_step1_kernel",
+        "kernel": {1: "ac2d_march1_kernel", 4: "ac2d_step2_1_kernel",
+                   5: "ac2d_step2_1_kernel"}.get(shape[3], "ac2d_step1_kernel"),
         "tile": hw.tile_label(shape),
+        "steps_per_launch": per,
+        "bytes_per_cell_launch": bytes_per_cell(storage, comp),
         "bytes_per_cell_step": head["bytes_per_cell"],
         "cells_per_launch": cells,
+        "launch_ms": head["kernel_ms"] * per,
         "kernel_ms": head["kernel_ms"],
+        # the throughput against the HBM roofline of a kernel that reads and
+        # writes the state every step (32 B per cell-step for fp16 +
+        # compensation and for fp32: 250 GLUPS at 8 TB/s)
+        "frac_of_one_step_roofline": head["glups"] * bytes_per_cell(storage, comp)
+        / PEAK_HBM_GBS,
     }
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     extra = {}
@@ -810,6 +833,7 @@ def main():
         "energy_drift_steps": head.get("full_run", {}).get("steps"),
         "vs_f32": (head["glups"] / f32["glups"]) if f32 else None,
         "variants": {k: {"glups": v["glups"], "ms_per_step": v["ms_per_step"],
+                         "steps_per_launch": v["steps_per_launch"],
                          "energy_drift_window": v["energy_drift_window"],
                          "energy_drift_vs_fp64": v.get("full_run", {}).get(
                              "energy_drift_vs_fp64"),
