@@ -178,7 +178,7 @@ static hipError_t step_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
     default:
         return hipErrorInvalidValue;   // two-step shapes: launch_ac2d_step2
     }
-    static_assert(kNumTiles2D == 11, "update the tile dispatch");
+    static_assert(kNumTiles2D == 12, "update the tile dispatch");
     return hipGetLastError();
 }
 

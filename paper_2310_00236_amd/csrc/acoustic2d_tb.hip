@@ -426,12 +426,12 @@ static hipError_t step2_tile(const Ac2dBatch &a, const Ac2dDesc *one, int tile,
             return hipErrorInvalidValue;                                          \
         }                                                                         \
     }
-        HW_TILE2(9) HW_TILE2(10)
+        HW_TILE2(9) HW_TILE2(10) HW_TILE2(11)
 #undef HW_TILE2
     default:
         return hipErrorInvalidValue;
     }
-    static_assert(kNumTiles2D == 11, "update the two-step tile dispatch");
+    static_assert(kNumTiles2D == 12, "update the two-step tile dispatch");
     return hipGetLastError();
 }
 

@@ -272,11 +272,15 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
     float *gm = lds + 6 * NG;             // mu, 2 planes (plane parity)
     float *gv = lds + 8 * NG;             // new velocities, 2 planes x 3
     enum : unsigned {
-        F_ACT = 1u, F_OWN = 2u, F_SXX = 4u, F_SYY = 8u, F_SZZ = 16u,
+        F_ACT = 1u, F_SXX = 4u, F_SYY = 8u, F_SZZ = 16u,
         F_SXZ = 32u, F_SYZ = 64u, F_VX = 128u, F_VY = 256u, F_VZ = 512u,
         F_MU = 1024u
     };
-    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    // the wavefront index in a scalar register: the flags of the row
+    // positions (q < M) are then wavefront-uniform and their tests scalar
+    // branches; only ownership (the grid's ragged edge) is decided per lane
+    const int tid = threadIdx.x, ln = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
     const int pitch = (int)d.pitch, slab = (int)d.slab;
     const float w = d.w;
@@ -301,6 +305,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
     // ---- positions and what each needs
     int off[NP], li[NP];
     unsigned fl[NP];
+    bool own[NP];          // the position is a cell of this column (F_OWN)
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         int lx, ly;
@@ -319,9 +324,8 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
         const bool rowm = ly < 0, colm = lx < 0, colp = lx == TX;
         const bool inx = lx >= 0 && lx < TX, iny = ly >= 0 && ly < TY;
         unsigned f = act ? F_ACT : 0u;
+        own[q] = act && inx && iny && x0 + lx < nx && y0 + ly < ny;
         if (act) {
-            if (inx && iny && x0 + lx < nx && y0 + ly < ny)
-                f |= F_OWN;
             if (!rowm)
                 f |= F_SXX | F_SXZ;
             if (!colm)
@@ -380,7 +384,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
                 in[q].v[2] = vin[2][a1];
             if (f & F_MU)
                 in[q].mu = MU[a1];
-            if (f & F_OWN)
+            if (own[q])
                 in[q].lam = LAM[o0 + off[q]];
         }
     };
@@ -440,7 +444,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
                 const float bb = 0.5f * (gb[l] + gb[l + 1]);
                 update_word<S, COMP>(cur[q].v[0], bb * g);
                 vxm[l] = val(cur[q].v[0]);
-                if (wr && (f & F_OWN))
+                if (wr && own[q])
                     __builtin_nontemporal_store(cur[q].v[0], vout[0] + om + off[q]);
             }
             if (f & F_VY) {   // vy at (i, j+1/2, k+1)
@@ -451,7 +455,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
                 const float bb = 0.5f * (gb[l] + gb[l + LS]);
                 update_word<S, COMP>(cur[q].v[1], bb * g);
                 vym[l] = val(cur[q].v[1]);
-                if (wr && (f & F_OWN))
+                if (wr && own[q])
                     __builtin_nontemporal_store(cur[q].v[1], vout[1] + om + off[q]);
             }
             if (f & F_VZ) {   // vz at (i, j, k+3/2)
@@ -462,7 +466,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
                 const float bb = 0.5f * (b_m[q] + cur[q].b);
                 update_word<S, COMP>(cur[q].v[2], bb * g);
                 vzm[l] = val(cur[q].v[2]);
-                if (wr && (f & F_OWN))
+                if (wr && own[q])
                     __builtin_nontemporal_store(cur[q].v[2], vout[2] + om + off[q]);
             }
         }
@@ -474,7 +478,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
             const float *mk = gm + pk * NG, *mm = gm + pm * NG;
 #pragma unroll
             for (int q = 0; q < M; ++q) {
-                if (!(fl[q] & F_OWN))
+                if (!own[q])
                     continue;
                 const int l = li[q];
                 const float ex = w * (vxk[l] - vxk[l - 1]);

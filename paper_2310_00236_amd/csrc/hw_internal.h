@@ -122,7 +122,7 @@ struct TileShape { int tx, ty, kind, tz; };
 constexpr TileShape kTiles2D[] = {{64, 16, 0, 1}, {64, 32, 0, 1}, {128, 16, 0, 1},
                                   {64, 64, 1, 1}, {64, 128, 1, 1}, {128, 64, 1, 1},
                                   {128, 128, 1, 1}, {64, 16, 3, 1}, {128, 16, 3, 1},
-                                  {64, 16, 4, 2}, {64, 32, 5, 2}};
+                                  {64, 16, 4, 2}, {64, 32, 5, 2}, {64, 24, 5, 2}};
 // Time steps one launch of a 2D shape advances.
 constexpr int steps_per_launch2d(const TileShape &t)
 {
