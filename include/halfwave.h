@@ -289,9 +289,9 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  *               passes (velocities, then stresses); one tx by ty tile per
  *               workgroup.
  * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
- * results.  Plans with HW_COMP_TWOSUM8 take kinds 0 and 3 only (HW_E_INVAL
- * for the others); in hw_batch_advance another tile argument runs their
- * group on shape 0.  Any of the output pointers may be NULL. */
+ * results.  Plans with HW_COMP_TWOSUM8 take every kind but 1 (HW_E_INVAL);
+ * in hw_batch_advance a kind-1 tile argument runs their group on shape 0.
+ * Any of the output pointers may be NULL. */
 int32_t hw_tile_count(int32_t physics);
 hw_status hw_tile_info(int32_t physics, int32_t tile, int32_t *tx,
                        int32_t *ty, int32_t *tz, int32_t *kind);

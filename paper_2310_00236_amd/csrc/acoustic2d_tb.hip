@@ -75,7 +75,10 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
                                            bool yin, Tb2Lds<ORDER, TY> &L)
 {
     using Gm = Tb2Geom<ORDER, TY>;
-    using WD = Word<S, COMP>;
+    // With 8-bit compensation words the value arrays hold values only and
+    // each cell's word is a byte comp_off bytes after its value array.
+    constexpr bool C8 = COMP == COMP_TWOSUM8;
+    using WD = Word<S, C8 ? COMP_NONE : COMP>;
     using W = typename WD::type;
     constexpr int TX = Gm::TX, R = Gm::R, H = Gm::H, G = Gm::G;
     constexpr int PW = Gm::PW, BW = Gm::BW, XW = Gm::XW, YW = Gm::YW;
@@ -96,6 +99,14 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     W HW_GLOBAL *__restrict__ p_out = gmem((W *)d.p[par ^ 1]);
     W HW_GLOBAL *__restrict__ vx_out = gmem((W *)d.vx[par ^ 1]);
     W HW_GLOBAL *__restrict__ vy_out = gmem((W *)d.vy[par ^ 1]);
+    using QP = const int8_t HW_GLOBAL *;
+    using QO = int8_t HW_GLOBAL *;
+    QP qp_in = gmem((const int8_t *)((const char *)d.p[par] + d.comp_off));
+    QP qx_in = gmem((const int8_t *)((const char *)d.vx[par] + d.comp_off));
+    QP qy_in = gmem((const int8_t *)((const char *)d.vy[par] + d.comp_off));
+    QO qp_out = gmem((int8_t *)((char *)d.p[par ^ 1] + d.comp_off));
+    QO qx_out = gmem((int8_t *)((char *)d.vx[par ^ 1] + d.comp_off));
+    QO qy_out = gmem((int8_t *)((char *)d.vy[par ^ 1] + d.comp_off));
     auto grow = [&](int r) { const int g = y0 + r; return yin ? g : wrapi(g, ny); };
     auto gcol = [&](int c) { const int g = x0 + c; return WX ? wrapi(g, nx) : g; };
     // LDS element of tile-relative (row, column) in each array
@@ -147,6 +158,8 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     float km[Q1 - Q0], bm[B1 - B0];
     W xhw = W(), yhw = W(), qhw = W();
     float qhk = 0.0f;
+    // 8-bit words of the kept cells (unused otherwise)
+    int8_t qpw[Q1 - Q0], qxw[Q1 - Q0], qyw[V1 - V0], qxh = 0, qyh = 0, qqh = 0;
 #pragma unroll
     for (int k = P0; k < P1; ++k) {
         const int r = row_of(k);
@@ -166,22 +179,40 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
             const int q = grow(r) * pitch;
             xw[k - Q0] = (vx_in + q)[col];
             km[k - Q0] = (kap + q)[col];
+            if constexpr (C8) {
+                qxw[k - Q0] = (qx_in + q)[col];
+                qpw[k - Q0] = (qp_in + q)[col];
+            }
         }
     }
 #pragma unroll
     for (int k = V0; k < V1; ++k) {
         const int r = row_of(k);
-        if (r >= -G && r < TY + H + R - 1)
-            yw[k - V0] = (vy_in + grow(r) * pitch)[col];
+        if (r >= -G && r < TY + H + R - 1) {
+            const int q = grow(r) * pitch;
+            yw[k - V0] = (vy_in + q)[col];
+            if constexpr (C8)
+                qyw[k - V0] = (qy_in + q)[col];
+        }
     }
-    if (xh_on)
-        xhw = vx_in[grow(xh.r) * pitch + gcol(xh.c)];
-    if (yh_on)
-        yhw = vy_in[grow(yh.r) * pitch + gcol(yh.c)];
+    if (xh_on) {
+        const int q = grow(xh.r) * pitch + gcol(xh.c);
+        xhw = vx_in[q];
+        if constexpr (C8)
+            qxh = qx_in[q];
+    }
+    if (yh_on) {
+        const int q = grow(yh.r) * pitch + gcol(yh.c);
+        yhw = vy_in[q];
+        if constexpr (C8)
+            qyh = qy_in[q];
+    }
     if (qh_on) {
         const int q = grow(qh.r) * pitch + gcol(qh.c);
         qhw = p_in[q];
         qhk = kap[q];
+        if constexpr (C8)
+            qqh = qp_in[q];
     }
     for (int e = tid; e < NPA + NPB; e += NT) {
         int r, c;
@@ -270,6 +301,18 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         return kk * dv;
     };
     auto p_inc = [&](int r, int c, float kk) { return p_at(X(r, c), Y(r, c), kk); };
+    // the update of Alg. 1/2 on a kept word (and its 8-bit word)
+    auto upd = [&](W &w, int8_t &q, float inc) {
+        if constexpr (C8)
+            update_store8<S>(w, q, inc);
+        else
+            update_one<S, COMP>(w, inc);
+    };
+    auto store8 = [&](QO base, int r, int8_t q) {
+        if constexpr (C8)
+            if (y0 + r < ny && (!WX || x0 + ln < nx))
+                __builtin_nontemporal_store(q, (base + (y0 + r) * pitch + x0) + (unsigned)ln);
+    };
     auto store = [&](W HW_GLOBAL *base, int r, const W &w) {
         if (y0 + r < ny && (!WX || x0 + ln < nx))
             __builtin_nontemporal_store(w, (base + (y0 + r) * pitch + x0) + (unsigned)ln);
@@ -280,7 +323,7 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = Q0; k < Q1; ++k) {
         const int r = row_of(k);
         if (r >= -H && r < TY + H) {
-            update_one<S, COMP>(xw[k - Q0], vx_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            upd(xw[k - Q0], qxw[k - Q0], vx_at(Pl + NW * k * PW, Bl + NW * k * BW));
             Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0]));
         }
     }
@@ -288,16 +331,16 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = V0; k < V1; ++k) {
         const int r = row_of(k);
         if (r >= -G && r < TY + H + R - 1) {
-            update_one<S, COMP>(yw[k - V0], vy_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            upd(yw[k - V0], qyw[k - V0], vy_at(Pl + NW * k * PW, Bl + NW * k * BW));
             Yl[NW * k * YW] = S::load(WD::v(yw[k - V0]));
         }
     }
     if (xh_on) {
-        update_one<S, COMP>(xhw, vx_inc(xh.r, xh.c));
+        upd(xhw, qxh, vx_inc(xh.r, xh.c));
         *X(xh.r, xh.c) = S::load(WD::v(xhw));
     }
     if (yh_on) {
-        update_one<S, COMP>(yhw, vy_inc(yh.r, yh.c));
+        upd(yhw, qyh, vy_inc(yh.r, yh.c));
         *Y(yh.r, yh.c) = S::load(WD::v(yhw));
     }
     __syncthreads();
@@ -309,12 +352,12 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         const int r = row_of(k);
         if (r >= -H && r < TY + H) {
             W &w = pw[k - P0];
-            update_one<S, COMP>(w, p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]));
+            upd(w, qpw[k - Q0], p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]));
             Pl[NW * k * PW] = S::load(WD::v(w));
         }
     }
     if (qh_on) {
-        update_one<S, COMP>(qhw, p_inc(qh.r, qh.c, qhk));
+        upd(qhw, qqh, p_inc(qh.r, qh.c, qhk));
         *P(qh.r, qh.c) = S::load(WD::v(qhw));
     }
     __syncthreads();
@@ -326,23 +369,26 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = Q0; k < Q1; ++k) {
         const int r = row_of(k);
         if (r >= 0 && r < TY) {
-            update_one<S, COMP>(xw[k - Q0], vx_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            upd(xw[k - Q0], qxw[k - Q0], vx_at(Pl + NW * k * PW, Bl + NW * k * BW));
             Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0]));
             store(vx_out, r, xw[k - Q0]);
+            store8(qx_out, r, qxw[k - Q0]);
         }
     }
 #pragma unroll
     for (int k = V0; k < V1; ++k) {
         const int r = row_of(k);
         if (r >= -R && r < TY + R - 1) {
-            update_one<S, COMP>(yw[k - V0], vy_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            upd(yw[k - V0], qyw[k - V0], vy_at(Pl + NW * k * PW, Bl + NW * k * BW));
             Yl[NW * k * YW] = S::load(WD::v(yw[k - V0]));
-            if (r >= 0 && r < TY)
+            if (r >= 0 && r < TY) {
                 store(vy_out, r, yw[k - V0]);
+                store8(qy_out, r, qyw[k - V0]);
+            }
         }
     }
     if (xh_on && xh.r >= 0 && xh.r < TY && xh.c >= -R && xh.c < TX + R - 1) {
-        update_one<S, COMP>(xhw, vx_inc(xh.r, xh.c));
+        upd(xhw, qxh, vx_inc(xh.r, xh.c));
         *X(xh.r, xh.c) = S::load(WD::v(xhw));
     }
     __syncthreads();
@@ -353,8 +399,9 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         const int r = row_of(k);
         if (r >= 0 && r < TY) {
             W &w = pw[k - P0];
-            update_one<S, COMP>(w, p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]));
+            upd(w, qpw[k - Q0], p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]));
             store(p_out, r, w);
+            store8(qp_out, r, qpw[k - Q0]);
         }
     }
 }
@@ -451,6 +498,10 @@ static hipError_t step2_comp(const Ac2dBatch &a, const Ac2dDesc *one, int comp,
     case COMP_NONE: return step2_order<S, COMP_NONE>(a, one, order, tile, s);
     case COMP_FAST2SUM: return step2_order<S, COMP_FAST2SUM>(a, one, order, tile, s);
     case COMP_TWOSUM: return step2_order<S, COMP_TWOSUM>(a, one, order, tile, s);
+    case COMP_TWOSUM8:
+        if constexpr (S::id != F32::id)
+            return step2_order<S, COMP_TWOSUM8>(a, one, order, tile, s);
+        break;
     }
     return hipErrorInvalidValue;
 }

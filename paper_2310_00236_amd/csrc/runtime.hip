@@ -320,10 +320,10 @@ constexpr int kGraphSteps = 32;
 static_assert(kGraphSteps % 4 == 0, "graph runs of an even number of launches");
 
 // The shape a group of plans sharing a kernel runs on when given `tile`:
-// acoustic plans with a point source or receivers, a non-default stencil or
-// 8-bit compensation words run on the one-step tile kernels -- shape 0,
-// except that 8-bit words keep a kind-3 shape -- and `single` asks for a
-// one-step shape (shape 0 in place of a two-step one).
+// acoustic plans with a point source or receivers or a non-default stencil
+// run on shape 0, 8-bit compensation words on any shape but the marching
+// kind 1 (else shape 0), and `single` asks for a one-step shape (shape 0 in
+// place of a two-step one).
 int group_tile(hw_plan *const *plans, int n, int tile, bool single)
 {
     const hw_plan *p0 = plans[0];
@@ -335,7 +335,7 @@ int group_tile(hw_plan *const *plans, int n, int tile, bool single)
     const int kind = kTiles2D[tile].kind;
     if (forced || p0->pb.stencil != HW_STENCIL_F32)
         return 0;
-    if (p0->pb.comp == HW_COMP_TWOSUM8 && kind != 0 && kind != 3)
+    if (p0->pb.comp == HW_COMP_TWOSUM8 && kind == 1)
         return 0;
     if (single && steps_per_launch2d(kTiles2D[tile]) != 1)
         return 0;
@@ -1355,9 +1355,9 @@ hw_status hw_plan_set_tile(hw_plan *p, int32_t tile)
     if (tile < 0 || tile >= num_tiles(p->pb))
         return fail(HW_E_INVAL, "tile index out of range");
     if (p->pb.physics == HW_ACOUSTIC2D && p->pb.comp == HW_COMP_TWOSUM8 &&
-        kTiles2D[tile].kind != 0 && kTiles2D[tile].kind != 3)
-        return fail(HW_E_INVAL, "8-bit compensation words run on the one-step tile "
-                                "kernels (kinds 0 and 3) only");
+        kTiles2D[tile].kind == 1)
+        return fail(HW_E_INVAL, "8-bit compensation words do not run on the marching "
+                                "kind 1");
     p->tile = tile;
     return HW_OK;
 }

@@ -116,3 +116,22 @@ def test_forced_plan_on_a_two_step_shape_runs_one_step_shapes():
     assert_bitexact(g, w, "forced")
     assert_bitexact(gc, wc, "forced comps")
     assert np.array_equal(rec, wrec)
+
+
+@pytest.mark.parametrize("tile", TWO)
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("order", [2, 4])
+def test_bitexact_8bit_words(tile, storage, order):
+    """8-bit compensation words on the two-step shapes: the value and the
+    byte of every cell of the intermediate state stay in registers; fields,
+    read-back compensation terms and energies as the oracle's."""
+    nx, ny = 150, 37
+    rho, kappa, dt, f = _case(nx, ny, order, storage, 341)
+    g, gc, ge = gpu_acoustic(nx, ny, order, storage, "twosum8", dt, rho, kappa, f, 25,
+                             energy_every=5, tile=tile)
+    w, wc, we = oracle_acoustic(nx, ny, order, storage, "twosum8", dt, rho, kappa, f, 25,
+                                energy_every=5)
+    assert_bitexact(g, w, "fields")
+    assert_bitexact(gc, wc, "comps")
+    assert any(np.any(wc[k] != 0) for k in wc)
+    np.testing.assert_allclose(ge, we, rtol=1e-12, atol=0)
