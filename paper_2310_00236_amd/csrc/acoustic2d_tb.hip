@@ -46,6 +46,17 @@ __device__ __forceinline__ Side side(int e)
     return Side{R0 + e / W, c < CL ? c - CL : TX + c - CL};
 }
 
+// An LDS address the compiler may not fold into the accesses made from it:
+// a stencil's reads then share one base register with small immediate
+// offsets (two paired reads from one add) instead of one add per pair.
+typedef __attribute__((address_space(3))) const float lds_f;
+__device__ __forceinline__ const lds_f *lds_base(const float *p)
+{
+    const lds_f *q = (const lds_f *)p;
+    __asm__("" : "+v"(q));
+    return q;
+}
+
 }  // namespace tb
 
 template <int ORDER, int TY>
@@ -258,39 +269,45 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
 
     // increments of the three updates from the LDS values, in the op order
     // of the one-step kernels
+    // (each stencil reads from a base at its lowest address: x offsets
+    // -1 .. 2 (vx), rows -1 .. 2 (vy), -2 .. 1 (p); order 2 uses 0 .. 1)
+    constexpr int LX = R - 1, LY = (R - 1) * PW;
     auto vx_at = [&](const float *pp, const float *bb) {
-        const float a0 = pp[1] - pp[0];
+        const tb::lds_f *q = tb::lds_base(pp - LX), *c = tb::lds_base(bb);
+        const float a0 = q[LX + 1] - q[LX];
         float g;
         if constexpr (ORDER == 4) {
-            const float a1 = pp[2] - pp[-1];
+            const float a1 = q[LX + 2] - q[LX - 1];
             g = w1 * a0 + w2 * a1;
         } else {
             g = w1 * a0;
         }
-        const float bx = 0.5f * (bb[0] + bb[1]);
+        const float bx = 0.5f * (c[0] + c[1]);
         return bx * g;
     };
     auto vx_inc = [&](int r, int c) { return vx_at(P(r, c), B(r, c)); };
     auto vy_at = [&](const float *pc, const float *bb) {
-        const float a0 = pc[PW] - pc[0];
+        const tb::lds_f *q = tb::lds_base(pc - LY), *c = tb::lds_base(bb);
+        const float a0 = q[LY + PW] - q[LY];
         float g;
         if constexpr (ORDER == 4) {
-            const float a1 = pc[2 * PW] - pc[-PW];
+            const float a1 = q[LY + 2 * PW] - q[LY - PW];
             g = w1 * a0 + w2 * a1;
         } else {
             g = w1 * a0;
         }
-        const float by = 0.5f * (bb[0] + bb[BW]);
+        const float by = 0.5f * (c[0] + c[BW]);
         return by * g;
     };
     auto vy_inc = [&](int r, int c) { return vy_at(P(r, c), B(r, c)); };
-    auto p_at = [&](const float *vr, const float *vc, float kk) {
-        const float ax0 = vr[0] - vr[-1];
-        const float ay0 = vc[0] - vc[-YW];
+    auto p_at = [&](const float *vr0, const float *vc0, float kk) {
+        const tb::lds_f *vr = tb::lds_base(vr0 - R), *vc = tb::lds_base(vc0 - R * YW);
+        const float ax0 = vr[R] - vr[R - 1];
+        const float ay0 = vc[R * YW] - vc[(R - 1) * YW];
         float gxv, gyv;
         if constexpr (ORDER == 4) {
-            const float ax1 = vr[1] - vr[-2];
-            const float ay1 = vc[YW] - vc[-2 * YW];
+            const float ax1 = vr[R + 1] - vr[R - 2];
+            const float ay1 = vc[(R + 1) * YW] - vc[(R - 2) * YW];
             gxv = w1 * ax0 + w2 * ax1;
             gyv = w1 * ay0 + w2 * ay1;
         } else {
