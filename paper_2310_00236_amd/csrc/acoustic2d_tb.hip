@@ -81,9 +81,12 @@ struct Tb2Lds {
     float ys[Gm::YR * Gm::YW];
 };
 
-template <class S, int COMP, int ORDER, int TY, int NW, bool WX>
+// EDGE: the tile lies within 2H cells of a grid edge (or the grid is
+// narrower than the tile): rows and columns wrap around the periodic grid and
+// stores skip cells past its end.  Interior tiles take neither step.
+template <class S, int COMP, int ORDER, int TY, int NW, bool EDGE>
 __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, int y0,
-                                           bool yin, Tb2Lds<ORDER, TY> &L)
+                                           Tb2Lds<ORDER, TY> &L)
 {
     using Gm = Tb2Geom<ORDER, TY>;
     // With 8-bit compensation words the value arrays hold values only and
@@ -118,8 +121,8 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     QO qp_out = gmem((int8_t *)((char *)d.p[par ^ 1] + d.comp_off));
     QO qx_out = gmem((int8_t *)((char *)d.vx[par ^ 1] + d.comp_off));
     QO qy_out = gmem((int8_t *)((char *)d.vy[par ^ 1] + d.comp_off));
-    auto grow = [&](int r) { const int g = y0 + r; return yin ? g : wrapi(g, ny); };
-    auto gcol = [&](int c) { const int g = x0 + c; return WX ? wrapi(g, nx) : g; };
+    auto grow = [&](int r) { const int g = y0 + r; return EDGE ? wrapi(g, ny) : g; };
+    auto gcol = [&](int c) { const int g = x0 + c; return EDGE ? wrapi(g, nx) : g; };
     // LDS element of tile-relative (row, column) in each array
     auto P = [&](int r, int c) { return L.ps + (r + 2 * H) * PW + (c + 2 * H); };
     auto B = [&](int r, int c) { return L.bs + (r + G) * BW + (c + G); };
@@ -225,31 +228,49 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         if constexpr (C8)
             qqh = qp_in[q];
     }
-    for (int e = tid; e < NPA + NPB; e += NT) {
-        int r, c;
-        if (e < NPA) {
-            const tb::Side s = tb::side<TX, -H, H, H>(e);
-            r = s.r;
-            c = s.c < 0 ? s.c - H : s.c + H;
-        } else {
-            const tb::Side s = tb::side<TX, 0, H, H>(e - NPA);
-            r = s.r < H ? s.r - 2 * H : TY + s.r;
-            c = s.c;
+    // the old-pressure and buoyancy frames: element e of each goes to
+    // thread e mod NT; loaded here with every other load (so the tile waits
+    // for memory once), written to LDS after the row values
+    constexpr int NPF = NPA + NPB, NBF = NBA + NBB;
+    constexpr int KP = cdiv(NPF, NT), KB = cdiv(NBF, NT);
+    W pfw[KP];
+    float bfv[KB];
+    int pfo[KP], bfo[KB];        // their LDS elements
+#pragma unroll
+    for (int i = 0; i < KP; ++i) {
+        const int e = tid + i * NT;
+        if (e < NPF) {
+            int r, c;
+            if (e < NPA) {
+                const tb::Side s = tb::side<TX, -H, H, H>(e);
+                r = s.r;
+                c = s.c < 0 ? s.c - H : s.c + H;
+            } else {
+                const tb::Side s = tb::side<TX, 0, H, H>(e - NPA);
+                r = s.r < H ? s.r - 2 * H : TY + s.r;
+                c = s.c;
+            }
+            pfw[i] = p_in[grow(r) * pitch + gcol(c)];
+            pfo[i] = (int)(P(r, c) - L.ps);
         }
-        *P(r, c) = S::load(WD::v(p_in[grow(r) * pitch + gcol(c)]));
     }
-    for (int e = tid; e < NBA + NBB; e += NT) {
-        int r, c;
-        if (e < NBA) {
-            const tb::Side s = tb::side<TX, -H, G, G>(e);
-            r = s.r;
-            c = s.c;
-        } else {
-            const tb::Side s = tb::side<TX, 0, H, H>(e - NBA);
-            r = s.r < R ? s.r - G : TY + H + (s.r - R);
-            c = s.c;
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+        const int e = tid + i * NT;
+        if (e < NBF) {
+            int r, c;
+            if (e < NBA) {
+                const tb::Side s = tb::side<TX, -H, G, G>(e);
+                r = s.r;
+                c = s.c;
+            } else {
+                const tb::Side s = tb::side<TX, 0, H, H>(e - NBA);
+                r = s.r < R ? s.r - G : TY + H + (s.r - R);
+                c = s.c;
+            }
+            bfv[i] = b[grow(r) * pitch + gcol(c)];
+            bfo[i] = (int)(B(r, c) - L.bs);
         }
-        *B(r, c) = b[grow(r) * pitch + gcol(c)];
     }
 #pragma unroll
     for (int k = P0; k < P1; ++k) {
@@ -263,6 +284,14 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         if (r >= -G && r < TY + G)
             Bl[NW * k * BW] = bm[k - B0];
     }
+#pragma unroll
+    for (int i = 0; i < KP; ++i)
+        if (tid + i * NT < NPF)
+            L.ps[pfo[i]] = S::load(WD::v(pfw[i]));
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+        if (tid + i * NT < NBF)
+            L.bs[bfo[i]] = bfv[i];
     if (qh_on)
         *P(qh.r, qh.c) = S::load(WD::v(qhw));
     __syncthreads();
@@ -272,34 +301,36 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     // (each stencil reads from a base at its lowest address: x offsets
     // -1 .. 2 (vx), rows -1 .. 2 (vy), -2 .. 1 (p); order 2 uses 0 .. 1)
     constexpr int LX = R - 1, LY = (R - 1) * PW;
-    auto vx_at = [&](const float *pp, const float *bb) {
-        const tb::lds_f *q = tb::lds_base(pp - LX), *c = tb::lds_base(bb);
+    // (the staggered buoyancy of a velocity cell is the same in both steps:
+    // the first step's value is kept in a register for the second)
+    auto vx_g = [&](const float *pp) {
+        const tb::lds_f *q = tb::lds_base(pp - LX);
         const float a0 = q[LX + 1] - q[LX];
-        float g;
         if constexpr (ORDER == 4) {
             const float a1 = q[LX + 2] - q[LX - 1];
-            g = w1 * a0 + w2 * a1;
+            return w1 * a0 + w2 * a1;
         } else {
-            g = w1 * a0;
+            return w1 * a0;
         }
-        const float bx = 0.5f * (c[0] + c[1]);
-        return bx * g;
     };
-    auto vx_inc = [&](int r, int c) { return vx_at(P(r, c), B(r, c)); };
-    auto vy_at = [&](const float *pc, const float *bb) {
-        const tb::lds_f *q = tb::lds_base(pc - LY), *c = tb::lds_base(bb);
+    auto bx_at = [&](const float *bb) {
+        const tb::lds_f *c = tb::lds_base(bb);
+        return 0.5f * (c[0] + c[1]);
+    };
+    auto vy_g = [&](const float *pc) {
+        const tb::lds_f *q = tb::lds_base(pc - LY);
         const float a0 = q[LY + PW] - q[LY];
-        float g;
         if constexpr (ORDER == 4) {
             const float a1 = q[LY + 2 * PW] - q[LY - PW];
-            g = w1 * a0 + w2 * a1;
+            return w1 * a0 + w2 * a1;
         } else {
-            g = w1 * a0;
+            return w1 * a0;
         }
-        const float by = 0.5f * (c[0] + c[BW]);
-        return by * g;
     };
-    auto vy_inc = [&](int r, int c) { return vy_at(P(r, c), B(r, c)); };
+    auto by_at = [&](const float *bb) {
+        const tb::lds_f *c = tb::lds_base(bb);
+        return 0.5f * (c[0] + c[BW]);
+    };
     auto p_at = [&](const float *vr0, const float *vc0, float kk) {
         const tb::lds_f *vr = tb::lds_base(vr0 - R), *vc = tb::lds_base(vc0 - R * YW);
         const float ax0 = vr[R] - vr[R - 1];
@@ -327,20 +358,22 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     };
     auto store8 = [&](QO base, int r, int8_t q) {
         if constexpr (C8)
-            if (y0 + r < ny && (!WX || x0 + ln < nx))
+            if (!EDGE || (y0 + r < ny && x0 + ln < nx))
                 __builtin_nontemporal_store(q, (base + (y0 + r) * pitch + x0) + (unsigned)ln);
     };
     auto store = [&](W HW_GLOBAL *base, int r, const W &w) {
-        if (y0 + r < ny && (!WX || x0 + ln < nx))
+        if (!EDGE || (y0 + r < ny && x0 + ln < nx))
             __builtin_nontemporal_store(w, (base + (y0 + r) * pitch + x0) + (unsigned)ln);
     };
 
     // ---- phase 2: v^{n+1/2} on the grown regions
+    float bxk[Q1 - Q0], byk[V1 - V0], bxh = 0.0f;
 #pragma unroll
     for (int k = Q0; k < Q1; ++k) {
         const int r = row_of(k);
         if (r >= -H && r < TY + H) {
-            upd(xw[k - Q0], qxw[k - Q0], vx_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            bxk[k - Q0] = bx_at(Bl + NW * k * BW);
+            upd(xw[k - Q0], qxw[k - Q0], bxk[k - Q0] * vx_g(Pl + NW * k * PW));
             Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0]));
         }
     }
@@ -348,16 +381,18 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = V0; k < V1; ++k) {
         const int r = row_of(k);
         if (r >= -G && r < TY + H + R - 1) {
-            upd(yw[k - V0], qyw[k - V0], vy_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            byk[k - V0] = by_at(Bl + NW * k * BW);
+            upd(yw[k - V0], qyw[k - V0], byk[k - V0] * vy_g(Pl + NW * k * PW));
             Yl[NW * k * YW] = S::load(WD::v(yw[k - V0]));
         }
     }
     if (xh_on) {
-        upd(xhw, qxh, vx_inc(xh.r, xh.c));
+        bxh = bx_at(B(xh.r, xh.c));
+        upd(xhw, qxh, bxh * vx_g(P(xh.r, xh.c)));
         *X(xh.r, xh.c) = S::load(WD::v(xhw));
     }
     if (yh_on) {
-        upd(yhw, qyh, vy_inc(yh.r, yh.c));
+        upd(yhw, qyh, by_at(B(yh.r, yh.c)) * vy_g(P(yh.r, yh.c)));
         *Y(yh.r, yh.c) = S::load(WD::v(yhw));
     }
     __syncthreads();
@@ -386,7 +421,7 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = Q0; k < Q1; ++k) {
         const int r = row_of(k);
         if (r >= 0 && r < TY) {
-            upd(xw[k - Q0], qxw[k - Q0], vx_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            upd(xw[k - Q0], qxw[k - Q0], bxk[k - Q0] * vx_g(Pl + NW * k * PW));
             Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0]));
             store(vx_out, r, xw[k - Q0]);
             store8(qx_out, r, qxw[k - Q0]);
@@ -396,7 +431,7 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = V0; k < V1; ++k) {
         const int r = row_of(k);
         if (r >= -R && r < TY + R - 1) {
-            upd(yw[k - V0], qyw[k - V0], vy_at(Pl + NW * k * PW, Bl + NW * k * BW));
+            upd(yw[k - V0], qyw[k - V0], byk[k - V0] * vy_g(Pl + NW * k * PW));
             Yl[NW * k * YW] = S::load(WD::v(yw[k - V0]));
             if (r >= 0 && r < TY) {
                 store(vy_out, r, yw[k - V0]);
@@ -405,7 +440,7 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         }
     }
     if (xh_on && xh.r >= 0 && xh.r < TY && xh.c >= -R && xh.c < TX + R - 1) {
-        upd(xhw, qxh, vx_inc(xh.r, xh.c));
+        upd(xhw, qxh, bxh * vx_g(P(xh.r, xh.c)));
         *X(xh.r, xh.c) = S::load(WD::v(xhw));
     }
     __syncthreads();
@@ -434,10 +469,10 @@ __device__ __forceinline__ void ac2d_tile2_entry(const Ac2dDesc &d, int par, int
     // every cell the tile touches lies within 2H cells of it
     const bool xin = x0 >= 2 * H && x0 + TX + 2 * H <= nx;
     const bool yin = y0 >= 2 * H && y0 + TY + 2 * H <= ny;
-    if (xin)
-        ac2d_tile2<S, COMP, ORDER, TY, NW, false>(d, par, x0, y0, yin, L);
+    if (xin && yin)
+        ac2d_tile2<S, COMP, ORDER, TY, NW, false>(d, par, x0, y0, L);
     else
-        ac2d_tile2<S, COMP, ORDER, TY, NW, true>(d, par, x0, y0, yin, L);
+        ac2d_tile2<S, COMP, ORDER, TY, NW, true>(d, par, x0, y0, L);
 }
 
 template <class S, int COMP, int ORDER, int TY, int NW>
