@@ -109,51 +109,69 @@ __device__ __forceinline__ void store_cells_nt(W HW_GLOBAL *p, const Cells<W, V>
     }
 }
 
-// Solution update of V adjacent cells.  For fp16 pairs the compensated sum
-// runs on packed half-precision instructions (two independent cells per
-// instruction, each lane correctly rounded, so the bits equal the scalar
-// definition); everything else goes cell by cell.
+// Solution updates of two independent cells (the words w0 and w1, the fp32
+// increments inc0 and inc1).  For fp16 they run on packed half-precision
+// instructions: two cells per instruction, each lane correctly rounded, so
+// the bits equal two scalar updates (update_store); the two narrowings of
+// the increments are one packed conversion, rounding to nearest even like
+// the scalar one.  Other formats go one cell after the other.
+template <class S, int COMP>
+__device__ __forceinline__ void update_pair(typename Word<S, COMP>::type &w0,
+                                            typename Word<S, COMP>::type &w1,
+                                            float inc0, float inc1)
+{
+    using WD = Word<S, COMP>;
+    if constexpr (S::id == F16::id) {
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const h2 v = {WD::v(w0), WD::v(w1)};
+        f2 a = {inc0, inc1};
+        if constexpr (COMP != COMP_NONE)
+            a = f2{inc0 + (float)WD::c(w0), inc1 + (float)WD::c(w1)};
+        __asm__("" : "+v"(a));        // no fusing into the narrowing (see opaque)
+        const h2 y = __builtin_convertvector(a, h2);
+        const h2 s = v + y;
+        if constexpr (COMP == COMP_NONE) {
+            w0 = WD::make(s[0], _Float16(0));
+            w1 = WD::make(s[1], _Float16(0));
+        } else {
+            h2 t;
+            if constexpr (COMP == COMP_FAST2SUM) {
+                const h2 z = s - v;
+                t = y - z;
+            } else {
+                const h2 pa = s - y;
+                const h2 pb = s - pa;
+                const h2 da = v - pa;
+                const h2 db = y - pb;
+                t = da + db;
+            }
+            w0 = WD::make(s[0], t[0]);
+            w1 = WD::make(s[1], t[1]);
+        }
+    } else {
+        auto v0 = WD::v(w0), c0 = WD::c(w0), v1 = WD::v(w1), c1 = WD::c(w1);
+        update_store<S, COMP>(v0, c0, inc0);
+        update_store<S, COMP>(v1, c1, inc1);
+        w0 = WD::make(v0, c0);
+        w1 = WD::make(v1, c1);
+    }
+}
+
+// Solution update of V adjacent cells: pairs of cells through update_pair
+// (packed for fp16), a last odd cell alone.
 template <class S, int COMP, int V>
 __device__ __forceinline__ void update_cells(Cells<typename Word<S, COMP>::type, V> &c,
                                              const float (&inc)[V])
 {
     using WD = Word<S, COMP>;
-    if constexpr (S::id == F16::id && V % 2 == 0) {
-        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int i = 0; i < V; i += 2) {
-            const h2 v = {WD::v(c.w[i]), WD::v(c.w[i + 1])};
-            if constexpr (COMP == COMP_NONE) {
-                const h2 r = {(_Float16)opaque(inc[i]), (_Float16)opaque(inc[i + 1])};
-                const h2 s = v + r;
-                c.w[i] = WD::make(s[0], _Float16(0));
-                c.w[i + 1] = WD::make(s[1], _Float16(0));
-            } else {
-                const h2 y = {(_Float16)opaque(inc[i] + (float)WD::c(c.w[i])),
-                              (_Float16)opaque(inc[i + 1] + (float)WD::c(c.w[i + 1]))};
-                const h2 s = v + y;
-                h2 t;
-                if constexpr (COMP == COMP_FAST2SUM) {
-                    const h2 z = s - v;
-                    t = y - z;
-                } else {
-                    const h2 pa = s - y;
-                    const h2 pb = s - pa;
-                    const h2 da = v - pa;
-                    const h2 db = y - pb;
-                    t = da + db;
-                }
-                c.w[i] = WD::make(s[0], t[0]);
-                c.w[i + 1] = WD::make(s[1], t[1]);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < V; ++i) {
-            auto v = WD::v(c.w[i]), cc = WD::c(c.w[i]);
-            update_store<S, COMP>(v, cc, inc[i]);
-            c.w[i] = WD::make(v, cc);
-        }
+    for (int i = 0; i + 1 < V; i += 2)
+        update_pair<S, COMP>(c.w[i], c.w[i + 1], inc[i], inc[i + 1]);
+    if constexpr (V % 2 == 1) {
+        auto v = WD::v(c.w[V - 1]), cc = WD::c(c.w[V - 1]);
+        update_store<S, COMP>(v, cc, inc[V - 1]);
+        c.w[V - 1] = WD::make(v, cc);
     }
 }
 
@@ -309,6 +327,7 @@ __device__ __forceinline__ void ac2d_tile(const Ac2dDesc &d, int par, int x0,
     // the wavefront index in a scalar register: row tests become scalar
     // branches and row offsets scalar arithmetic
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __builtin_assume(wv >= 0 && wv < NW);    // (the range the copy hides)
     const int ln = threadIdx.x & 63;
     const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
     using A = Sten<S, SP>;

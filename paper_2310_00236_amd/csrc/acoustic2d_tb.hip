@@ -57,6 +57,11 @@ __device__ __forceinline__ const lds_f *lds_base(const float *p)
     return q;
 }
 
+// A compile-time slot bound passed to a generic lambda.
+template <int N> struct IC {
+    static constexpr int value = N;
+};
+
 }  // namespace tb
 
 template <int ORDER, int TY>
@@ -102,6 +107,10 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     // register, the row tests below are scalar branches and the row parts of
     // addresses scalar offsets
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // (its range, which the scalar copy hides from the compiler: the slots
+    // whose rows lie inside a phase's region for every wavefront then need
+    // no test at all)
+    __builtin_assume(wv >= 0 && wv < NW);
     const int ln = threadIdx.x & 63, tid = threadIdx.x;
     const int nx = (int)d.nx, ny = (int)d.ny, pitch = (int)d.pitch;
     const float w1 = d.w1, w2 = d.w2;
@@ -356,6 +365,48 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         else
             update_one<S, COMP>(w, inc);
     };
+    // Visits the register slots [K0, K1) whose rows pass on(k).  For fp16
+    // words, where two neighbouring slots both do, their increments are
+    // computed first and the two words updated together on packed
+    // instructions (update_pair: the same bits as two single updates);
+    // otherwise slot by slot.  fin(k) follows each slot's update.
+    constexpr bool PAIR = S::id == F16::id && !C8;
+    auto walk = [&](auto k0c, auto k1c, auto on, auto inc, auto wd, auto qb, auto fin) {
+        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+        if constexpr (PAIR) {
+#pragma unroll
+            for (int k = K0; k < K1; k += 2) {
+                const int k1 = k + 1 < K1 ? k + 1 : k;
+                const bool a = on(k), b = k + 1 < K1 && on(k1);
+                if (a && b) {
+                    const float i0 = inc(k), i1 = inc(k1);
+                    update_pair<S, COMP>(wd(k), wd(k1), i0, i1);
+                    fin(k);
+                    fin(k1);
+                } else {
+                    if (a) {
+                        upd(wd(k), qb(k), inc(k));
+                        fin(k);
+                    }
+                    if (b) {
+                        upd(wd(k1), qb(k1), inc(k1));
+                        fin(k1);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = K0; k < K1; ++k)
+                if (on(k)) {
+                    upd(wd(k), qb(k), inc(k));
+                    fin(k);
+                }
+        }
+    };
+    using IQ0 = tb::IC<Q0>;
+    using IQ1 = tb::IC<Q1>;
+    using IV0 = tb::IC<V0>;
+    using IV1 = tb::IC<V1>;
     auto store8 = [&](QO base, int r, int8_t q) {
         if constexpr (C8)
             if (!EDGE || (y0 + r < ny && x0 + ln < nx))
@@ -368,24 +419,32 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
 
     // ---- phase 2: v^{n+1/2} on the grown regions
     float bxk[Q1 - Q0], byk[V1 - V0], bxh = 0.0f;
-#pragma unroll
-    for (int k = Q0; k < Q1; ++k) {
-        const int r = row_of(k);
-        if (r >= -H && r < TY + H) {
-            bxk[k - Q0] = bx_at(Bl + NW * k * BW);
-            upd(xw[k - Q0], qxw[k - Q0], bxk[k - Q0] * vx_g(Pl + NW * k * PW));
-            Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0]));
-        }
-    }
-#pragma unroll
-    for (int k = V0; k < V1; ++k) {
-        const int r = row_of(k);
-        if (r >= -G && r < TY + H + R - 1) {
-            byk[k - V0] = by_at(Bl + NW * k * BW);
-            upd(yw[k - V0], qyw[k - V0], byk[k - V0] * vy_g(Pl + NW * k * PW));
-            Yl[NW * k * YW] = S::load(WD::v(yw[k - V0]));
-        }
-    }
+    auto xwd = [&](int k) -> W & { return xw[k - Q0]; };
+    auto xqb = [&](int k) -> int8_t & { return qxw[k - Q0]; };
+    auto ywd = [&](int k) -> W & { return yw[k - V0]; };
+    auto yqb = [&](int k) -> int8_t & { return qyw[k - V0]; };
+    auto pwd = [&](int k) -> W & { return pw[k - P0]; };
+    auto pqb = [&](int k) -> int8_t & { return qpw[k - Q0]; };
+    auto xlds = [&](int k) { Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0])); };
+    auto ylds = [&](int k) { Yl[NW * k * YW] = S::load(WD::v(yw[k - V0])); };
+    auto vx_slot = [&](int k) { return bxk[k - Q0] * vx_g(Pl + NW * k * PW); };
+    auto vy_slot = [&](int k) { return byk[k - V0] * vy_g(Pl + NW * k * PW); };
+    auto p_slot = [&](int k) {
+        return p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]);
+    };
+    walk(IQ0(), IQ1(), [&](int k) { const int r = row_of(k); return r >= -H && r < TY + H; },
+         [&](int k) {
+             bxk[k - Q0] = bx_at(Bl + NW * k * BW);
+             return vx_slot(k);
+         },
+         xwd, xqb, xlds);
+    walk(IV0(), IV1(),
+         [&](int k) { const int r = row_of(k); return r >= -G && r < TY + H + R - 1; },
+         [&](int k) {
+             byk[k - V0] = by_at(Bl + NW * k * BW);
+             return vy_slot(k);
+         },
+         ywd, yqb, ylds);
     if (xh_on) {
         bxh = bx_at(B(xh.r, xh.c));
         upd(xhw, qxh, bxh * vx_g(P(xh.r, xh.c)));
@@ -399,15 +458,9 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
 
     // ---- phase 3: p^{n+1} on the tile grown by H; its values replace the
     // old pressure values in LDS (phase 2 has finished reading them)
-#pragma unroll
-    for (int k = Q0; k < Q1; ++k) {
-        const int r = row_of(k);
-        if (r >= -H && r < TY + H) {
-            W &w = pw[k - P0];
-            upd(w, qpw[k - Q0], p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]));
-            Pl[NW * k * PW] = S::load(WD::v(w));
-        }
-    }
+    walk(IQ0(), IQ1(), [&](int k) { const int r = row_of(k); return r >= -H && r < TY + H; },
+         p_slot, pwd, pqb,
+         [&](int k) { Pl[NW * k * PW] = S::load(WD::v(pw[k - P0])); });
     if (qh_on) {
         upd(qhw, qqh, p_inc(qh.r, qh.c, qhk));
         *P(qh.r, qh.c) = S::load(WD::v(qhw));
@@ -417,28 +470,21 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     // ---- phase 4: v^{n+3/2} on the cells the tile's new pressure needs --
     // vx on rows [0, TY), columns [-R, TX+R-1); vy on rows [-R, TY+R-1),
     // columns [0, TX) -- and the tile's own cells stored
-#pragma unroll
-    for (int k = Q0; k < Q1; ++k) {
-        const int r = row_of(k);
-        if (r >= 0 && r < TY) {
-            upd(xw[k - Q0], qxw[k - Q0], bxk[k - Q0] * vx_g(Pl + NW * k * PW));
-            Xl[NW * k * XW] = S::load(WD::v(xw[k - Q0]));
-            store(vx_out, r, xw[k - Q0]);
-            store8(qx_out, r, qxw[k - Q0]);
-        }
-    }
-#pragma unroll
-    for (int k = V0; k < V1; ++k) {
-        const int r = row_of(k);
-        if (r >= -R && r < TY + R - 1) {
-            upd(yw[k - V0], qyw[k - V0], byk[k - V0] * vy_g(Pl + NW * k * PW));
-            Yl[NW * k * YW] = S::load(WD::v(yw[k - V0]));
-            if (r >= 0 && r < TY) {
-                store(vy_out, r, yw[k - V0]);
-                store8(qy_out, r, qyw[k - V0]);
-            }
-        }
-    }
+    walk(IQ0(), IQ1(), [&](int k) { const int r = row_of(k); return r >= 0 && r < TY; },
+         vx_slot, xwd, xqb, [&](int k) {
+             xlds(k);
+             store(vx_out, row_of(k), xw[k - Q0]);
+             store8(qx_out, row_of(k), qxw[k - Q0]);
+         });
+    walk(IV0(), IV1(), [&](int k) { const int r = row_of(k); return r >= -R && r < TY + R - 1; },
+         vy_slot, ywd, yqb, [&](int k) {
+             ylds(k);
+             const int r = row_of(k);
+             if (r >= 0 && r < TY) {
+                 store(vy_out, r, yw[k - V0]);
+                 store8(qy_out, r, qyw[k - V0]);
+             }
+         });
     if (xh_on && xh.r >= 0 && xh.r < TY && xh.c >= -R && xh.c < TX + R - 1) {
         upd(xhw, qxh, bxh * vx_g(P(xh.r, xh.c)));
         *X(xh.r, xh.c) = S::load(WD::v(xhw));
@@ -446,16 +492,11 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     __syncthreads();
 
     // ---- phase 5: p^{n+2} on the tile
-#pragma unroll
-    for (int k = Q0; k < Q1; ++k) {
-        const int r = row_of(k);
-        if (r >= 0 && r < TY) {
-            W &w = pw[k - P0];
-            upd(w, qpw[k - Q0], p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0]));
-            store(p_out, r, w);
-            store8(qp_out, r, qpw[k - Q0]);
-        }
-    }
+    walk(IQ0(), IQ1(), [&](int k) { const int r = row_of(k); return r >= 0 && r < TY; },
+         p_slot, pwd, pqb, [&](int k) {
+             store(p_out, row_of(k), pw[k - P0]);
+             store8(qp_out, row_of(k), qpw[k - Q0]);
+         });
 }
 
 template <class S, int COMP, int ORDER, int TY, int NW>

@@ -281,6 +281,7 @@ __device__ __forceinline__ void el3d_fused(const El3dDesc &d, int par, int x0,
     // branches; only ownership (the grid's ragged edge) is decided per lane
     const int tid = threadIdx.x, ln = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    __builtin_assume(wv >= 0 && wv < 4);     // (the range the copy hides)
     const int nx = (int)d.nx, ny = (int)d.ny, nz = (int)d.nz;
     const int pitch = (int)d.pitch, slab = (int)d.slab;
     const float w = d.w;
