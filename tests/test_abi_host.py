@@ -12,7 +12,34 @@ import paper_2310_00236_amd as hw
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include",
                       "halfwave.h")
-FAKE_ARENA = 1 << 20      # aligned non-NULL address; never dereferenced here
+FAKE_ARENA = 1 << 20      # aligned non-NULL address, for machines without a GPU
+
+
+def _gpu_visible():
+    # counting devices does not initialise one
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+_GPU = _gpu_visible()
+_arenas = []
+
+
+def _arena_address(nbytes):
+    """The arena handed to hw_plan_create.  Without a GPU, an aligned address
+    that no call here dereferences: every call either stops at host-side
+    validation or fails for want of a device.  Where a GPU is visible, the
+    calls that pass validation go on to the device and write the arena, so
+    it must be real device memory (kept alive until the session ends)."""
+    if not _GPU:
+        return FAKE_ARENA
+    import torch
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda:0")
+    _arenas.append(t)
+    return (t.data_ptr() + 255) // 256 * 256
 
 
 def declared_functions():
@@ -104,7 +131,7 @@ def test_footprint_grows_with_precision_and_compensation():
 def _plan(pb, arena_bytes=None):
     h = ctypes.c_void_p()
     n = hw.footprint(pb) if arena_bytes is None else arena_bytes
-    st = hw.lib().hw_plan_create(ctypes.byref(pb.c()), ctypes.c_void_p(FAKE_ARENA),
+    st = hw.lib().hw_plan_create(ctypes.byref(pb.c()), ctypes.c_void_p(_arena_address(n)),
                                  n, ctypes.byref(h))
     return st, h
 
@@ -114,7 +141,8 @@ def test_plan_create_checks_arena():
     st, _ = _plan(pb, hw.footprint(pb) - 1)
     assert st == 4                                   # HW_E_NOMEM
     h = ctypes.c_void_p()
-    st = hw.lib().hw_plan_create(ctypes.byref(pb.c()), ctypes.c_void_p(FAKE_ARENA + 8),
+    st = hw.lib().hw_plan_create(ctypes.byref(pb.c()),
+                                 ctypes.c_void_p(_arena_address(hw.footprint(pb)) + 8),
                                  hw.footprint(pb), ctypes.byref(h))
     assert st == 1 and not h.value                   # misaligned: INVAL
     st, h = _plan(pb)
