@@ -227,9 +227,11 @@ hw_status hw_get_fields(hw_plan *plan, double *const *fields,
  * by 2^scale_log2 if the plan uses a field scale).  nsamples = 0 removes the
  * source.  The sample is rounded to fp32 on the host (and to the storage
  * format inside the step when the plan's stencil is HW_STENCIL_STORAGE).
- * A plan with a source, receivers or a non-default stencil steps with
- * kernel shape 0 whatever its hw_plan_set_tile setting (the shapes give
- * identical bits).
+ * A plan with a source or receivers steps on its hw_plan_set_tile shape if
+ * that is a two-step shape (kinds 4 and 5, which compile the same source
+ * and recording code), else on kernel shape 0; a plan with a non-default
+ * stencil steps on shape 0 whatever its setting (the shapes give identical
+ * bits).
  * 2D elastic plans: the source acts on vy at (ix, iy+1/2), 0 <= iy <= ny-2
  * (the s^{vy} term of Eq. A1): the sample is added to the velocity
  * increment after the multiplication by the staggered buoyancy.

@@ -19,8 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhalfwave.so")
-SOURCES = ["acoustic2d.hip", "acoustic2d_var.hip", "acoustic2d_tb.hip", "elastic3d.hip",
-           "elastic2d.hip", "runtime.hip", "convert.hip"]
+SOURCES = ["acoustic2d.hip", "acoustic2d_var.hip", "acoustic2d_tb.hip", "acoustic2d_tb_var.hip",
+           "elastic3d.hip", "elastic2d.hip", "runtime.hip", "convert.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

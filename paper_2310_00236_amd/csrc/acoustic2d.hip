@@ -29,7 +29,7 @@ __global__ void tick_kernel(const StepCounters c)
 {
     const int i = threadIdx.x;
     if (i < c.n)
-        c.c[i][0] += 1;
+        c.c[i][0] += c.by;
 }
 
 __global__ void set_counter_kernel(int64_t *c, int64_t v)

@@ -250,10 +250,11 @@ __device__ __forceinline__ void update_one(typename Word<S, COMP>::type &w, doub
     w = WD::make(v, c);
 }
 
-// Point source and receivers of one plan in the current step (Sec. 3: the
-// s_p term of Eq. 1, and the receivers' time histories).  The plan's
-// device step counter tells which sample and which trace row this step
-// uses; it is read only when the plan has a source or receivers.
+// Point source and receivers of one plan in the current step, or `ahead`
+// steps after it (Sec. 3: the s_p term of Eq. 1, and the receivers' time
+// histories).  The plan's device step counter tells which sample and which
+// trace row the step uses; it is read only when the plan has a source or
+// receivers.
 struct Forcing {
     bool src;        // the source is active in this step
     float s;         // its sample (fp32)
@@ -262,11 +263,11 @@ struct Forcing {
     int64_t row;     // their trace row
 };
 
-__device__ __forceinline__ Forcing forcing(const Ac2dDesc &d)
+__device__ __forceinline__ Forcing forcing(const Ac2dDesc &d, int ahead = 0)
 {
     Forcing f{false, 0.0f, d.src_x, d.src_y, 0, 0};
     if (d.src_n > 0 || d.rec_n > 0) {
-        const int64_t n = *gmem(d.step);
+        const int64_t n = *gmem(d.step) + ahead;
         if (n < d.src_n) {
             f.src = true;
             f.s = gmem(d.src)[n];

@@ -152,10 +152,14 @@ hipError_t launch_ac2d_step(const Ac2dBatch &a, const Ac2dDesc *one, int storage
 hipError_t launch_ac2d_variant(const Ac2dBatch &a, const Ac2dDesc *one, int format,
                                int comp, int order, int tile, int stencil,
                                hipStream_t s);
-// Two steps per launch (tile shapes of kind 4 and 5; no 8-bit compensation
-// words, no source, receivers or stencil variants).
+// Two steps per launch (tile shapes of kind 4 and 5; every storage and
+// compensation, no stencil variants).  `forced`: some shot has a point
+// source or receivers (their plans' step counters then advance by two per
+// launch).  The forcing kernels sit in their own translation unit.
 hipError_t launch_ac2d_step2(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
-                             int comp, int order, int tile, hipStream_t s);
+                             int comp, int order, int tile, bool forced, hipStream_t s);
+hipError_t launch_ac2d_step2_forcing(const Ac2dBatch &a, const Ac2dDesc *one, int storage,
+                                     int comp, int order, int tile, hipStream_t s);
 hipError_t launch_ac2d_energy(const Ac2dDesc *d_desc, int parity,
                               int64_t ny, int storage, int order, int stride,
                               double *partial, hipStream_t s);
@@ -177,7 +181,9 @@ hipError_t launch_energy_finish(const double *partial, int64_t n,
                                 hipStream_t s);
 // Advance the device step counters of n plans by one (n <= kMaxBatch);
 // set one counter to a value.
-struct StepCounters { int64_t *c[kMaxBatch]; int32_t n; };
+// Step counters of plans with a source or receivers, each advanced by `by`
+// (the steps of the launch before it).
+struct StepCounters { int64_t *c[kMaxBatch]; int32_t n; int32_t by = 1; };
 hipError_t launch_tick(const StepCounters &c, hipStream_t s);
 hipError_t launch_set_counter(int64_t *c, int64_t value, hipStream_t s);
 

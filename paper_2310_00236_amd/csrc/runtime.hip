@@ -333,11 +333,16 @@ int group_tile(hw_plan *const *plans, int n, int tile, bool single)
     for (int i = 0; i < n; ++i)
         forced = forced || plans[i]->counts();
     const int kind = kTiles2D[tile].kind;
-    if (forced || p0->pb.stencil != HW_STENCIL_F32)
+    const bool two = steps_per_launch2d(kTiles2D[tile]) == 2;
+    if (p0->pb.stencil != HW_STENCIL_F32)
         return 0;
+    if (single && two)
+        return 0;
+    // plans with a point source or receivers: the two-step kernels, or the
+    // one-step variant kernels of shape 0
+    if (forced)
+        return two ? tile : 0;
     if (p0->pb.comp == HW_COMP_TWOSUM8 && kind == 1)
-        return 0;
-    if (single && steps_per_launch2d(kTiles2D[tile]) != 1)
         return 0;
     return tile;
 }
@@ -414,7 +419,8 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             a.total_tiles = (int32_t)total;
             if (steps_per_launch2d(kTiles2D[t]) == 2)
                 e = launch_ac2d_step2(a, m == 1 ? &plans[base]->h2 : nullptr,
-                                      p0->pb.storage, p0->pb.comp, p0->pb.order, t, s);
+                                      p0->pb.storage, p0->pb.comp, p0->pb.order, t, forced,
+                                      s);
             else
                 e = launch_ac2d_step(a, m == 1 ? &plans[base]->h2 : nullptr,
                                      p0->pb.storage, p0->pb.comp, p0->pb.order, t,
@@ -422,6 +428,7 @@ hw_status launch_group_raw(hw_plan *const *plans, int n, int tile,
             // plans with a source or receivers count their steps on the device
             StepCounters c;
             c.n = 0;
+            c.by = steps_per_launch2d(kTiles2D[t]);
             for (int i = 0; i < m; ++i)
                 if (plans[base + i]->counts())
                     c.c[c.n++] = plans[base + i]->counter;

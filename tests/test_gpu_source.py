@@ -31,7 +31,7 @@ def _setup(order, storage, seed=601):
 
 
 def _gpu(order, storage, comp, rho, kappa, dt, f, nsteps, samples, recs, tile=0,
-         energy_every=0):
+         energy_every=0, src=SRC):
     ntrace = (nsteps // energy_every + 2) if energy_every else 0
     pb = hw.Problem("acoustic2d", NX, NY, 1, order, storage, comp, 1.0, dt, 0,
                     ntrace, src_cap=len(samples), rec_cap=len(recs),
@@ -40,7 +40,7 @@ def _gpu(order, storage, comp, rho, kappa, dt, f, nsteps, samples, recs, tile=0,
     plan.set_tile(tile)
     plan.set_material([rho, kappa])
     plan.set_fields(f)
-    plan.set_source(SRC[0], SRC[1], samples)
+    plan.set_source(src[0], src[1], samples)
     plan.set_receivers(recs)
     plan.advance(nsteps, energy_every)
     out, comps = plan.get_fields(comps=True)
@@ -51,12 +51,20 @@ def _gpu(order, storage, comp, rho, kappa, dt, f, nsteps, samples, recs, tile=0,
 
 
 def _oracle(order, storage, comp, rho, kappa, dt, f, nsteps, samples, recs,
-            energy_every=0):
+            energy_every=0, src=SRC):
     fr = {k: oracle.round_to(v, storage) for k, v in f.items()}
     return oracle.acoustic2d(NX, NY, order, 1.0, dt, rho, kappa, fr,
                              storage=storage, stencil="f32", comp=comp,
                              nsteps=nsteps, energy_every=energy_every,
-                             source=(SRC[0], SRC[1], samples), receivers=recs)
+                             source=(src[0], src[1], samples), receivers=recs)
+
+
+def _shape_index(shape):
+    return next(i for i, t in enumerate(hw.tiles("acoustic2d")) if tuple(t) == shape)
+
+
+# tile shapes that advance two steps per launch
+TWO_STEP = [i for i, t in enumerate(hw.tiles("acoustic2d")) if t[2] == 2]
 
 
 @pytest.mark.parametrize("storage,comp,order", [
@@ -81,7 +89,8 @@ def test_bitexact_source_and_receivers(storage, comp, order):
 
 @pytest.mark.parametrize("tile", range(len(hw.tiles("acoustic2d"))))
 def test_every_tile_shape(tile):
-    """Any tile setting: forced plans step with kernel shape 0."""
+    """Any tile setting: forced plans step with kernel shape 0, or on their
+    two-step shape."""
     rho, kappa, dt, f = _setup(4, "f16", 611)
     samples = _samples(20, dt)
     g, gc, gt, _ = _gpu(4, "f16", "twosum", rho, kappa, dt, f, 24, samples, RECS,
@@ -92,9 +101,52 @@ def test_every_tile_shape(tile):
     assert np.array_equal(gt, wt)
 
 
-def test_batched_with_and_without_sources():
+@pytest.mark.parametrize("storage,comp,order", [
+    ("f32", "none", 4), ("f16", "none", 2), ("f16", "twosum", 4), ("f16", "fast2sum", 4),
+    ("bf16", "twosum", 4), ("f16", "twosum8", 4), ("bf16", "twosum8", 2)])
+def test_two_step_source_and_receivers(storage, comp, order):
+    """Two steps per launch (64 x 24) with the point source and receivers:
+    45 steps in chunks of 15 between energy logs (odd chunks end with a
+    one-step launch), the source active for the first 30; fields,
+    compensation terms, receiver traces and energies as the oracle's."""
+    rho, kappa, dt, f = _setup(order, storage, 641)
+    samples = _samples(30, dt)
+    tile = _shape_index((64, 24, 2, 5))
+    g, gc, gt, ge = _gpu(order, storage, comp, rho, kappa, dt, f, 45, samples,
+                         RECS, tile=tile, energy_every=15)
+    w, wc, we, wt = _oracle(order, storage, comp, rho, kappa, dt, f, 45, samples,
+                            RECS, energy_every=15)
+    assert_bitexact(g, w, "fields")
+    if comp != "none":
+        assert_bitexact(gc, wc, "comps")
+    assert np.array_equal(gt, wt), np.argwhere(gt != wt)[:5]
+    np.testing.assert_allclose(ge, we, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("tile", TWO_STEP)
+@pytest.mark.parametrize("src", [(63, 23), (64, 24), (66, 15), (0, 36), (149, 0)])
+def test_two_step_source_on_tile_edges(tile, src):
+    """The source on or next to a tile's edge, where neighbouring workgroups
+    recompute its cell's intermediate pressure in their grown regions, and on
+    the grid's corners (periodic wrap): 25 steps (the last a one-step
+    launch) as the oracle's, receivers around the source included."""
+    rho, kappa, dt, f = _setup(4, "f16", 651)
+    samples = _samples(21, dt)
+    recs = [src, ((src[0] + 1) % NX, src[1]), (src[0], (src[1] + NY - 1) % NY), (0, 0)]
+    g, gc, gt, _ = _gpu(4, "f16", "twosum", rho, kappa, dt, f, 25, samples, recs,
+                        tile=tile, src=src)
+    w, wc, _, wt = _oracle(4, "f16", "twosum", rho, kappa, dt, f, 25, samples, recs,
+                           src=src)
+    assert_bitexact(g, w, f"tile {tile} source {src}")
+    assert_bitexact(gc, wc, f"tile {tile} source {src} comps")
+    assert np.array_equal(gt, wt), np.argwhere(gt != wt)[:5]
+
+
+@pytest.mark.parametrize("tile", [0, _shape_index((64, 24, 2, 5))])
+def test_batched_with_and_without_sources(tile):
     """A batch mixing a forced plan, an unforced one and a receivers-only
-    one, with uneven step counts: each ends as the oracle says."""
+    one, with uneven step counts, on the one-step shape 0 and on a two-step
+    shape: each ends as the oracle says."""
     rho, kappa, dt, f = _setup(4, "f16", 621)
     samples = _samples(25, dt)
 
@@ -112,7 +164,7 @@ def test_batched_with_and_without_sources():
 
     specs = [(True, True, 40), (False, False, 35), (False, True, 50)]
     plans = [make(*s) for s in specs]
-    hw.batch_advance(plans, [s[2] for s in specs], tile=0)
+    hw.batch_advance(plans, [s[2] for s in specs], tile=tile)
     fr = {k: oracle.round_to(v, "f16") for k, v in f.items()}
     for p, (src, recs, n) in zip(plans, specs):
         out = oracle.acoustic2d(NX, NY, 4, 1.0, dt, rho, kappa, fr, storage="f16",
