@@ -361,7 +361,9 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
         const tb::lds_f *c = tb::lds_base(bb);
         return 0.5f * (c[0] + c[BW]);
     };
-    auto p_at = [&](const float *vr0, const float *vc0, float kk) {
+    // the pressure increment; with `src` (the cell is the source cell of the
+    // step) the sample s joins the right-hand side before the scaling
+    auto p_at = [&](const float *vr0, const float *vc0, float kk, bool src, float s) {
         const tb::lds_f *vr = tb::lds_base(vr0 - R), *vc = tb::lds_base(vc0 - R * YW);
         const float ax0 = vr[R] - vr[R - 1];
         const float ay0 = vc[R * YW] - vc[(R - 1) * YW];
@@ -375,36 +377,14 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
             gxv = w1 * ax0;
             gyv = w1 * ay0;
         }
-        const float dv = gxv + gyv;
-        return kk * dv;
-    };
-    // the same with the source sample of the step joining the right-hand
-    // side before the scaling, where `src` says the cell is the source cell
-    auto p_at_src = [&](const float *vr0, const float *vc0, float kk, bool src, float s) {
-        if constexpr (!FRC) {
-            return p_at(vr0, vc0, kk);
-        } else {
-            const tb::lds_f *vr = tb::lds_base(vr0 - R), *vc = tb::lds_base(vc0 - R * YW);
-            const float ax0 = vr[R] - vr[R - 1];
-            const float ay0 = vc[R * YW] - vc[(R - 1) * YW];
-            float gxv, gyv;
-            if constexpr (ORDER == 4) {
-                const float ax1 = vr[R + 1] - vr[R - 2];
-                const float ay1 = vc[(R + 1) * YW] - vc[(R - 2) * YW];
-                gxv = w1 * ax0 + w2 * ax1;
-                gyv = w1 * ay0 + w2 * ay1;
-            } else {
-                gxv = w1 * ax0;
-                gyv = w1 * ay0;
-            }
-            float dv = gxv + gyv;
+        float dv = gxv + gyv;
+        if constexpr (FRC)
             if (src)
                 dv = dv + s;
-            return kk * dv;
-        }
+        return kk * dv;
     };
     auto p_inc = [&](int r, int c, float kk) {
-        return p_at_src(X(r, c), Y(r, c), kk, src_at(f0, gcol(c), grow(r)), f0.s);
+        return p_at(X(r, c), Y(r, c), kk, src_at(f0, gcol(c), grow(r)), f0.s);
     };
     // the update of Alg. 1/2 on a kept word (and its 8-bit word)
     auto upd = [&](W &w, int8_t &q, float inc) {
@@ -488,8 +468,8 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     auto vy_slot = [&](int k) { return byk[k - V0] * vy_g(Pl + NW * k * PW); };
     // the pressure increment of slot k in the step of forcing f
     auto p_slot = [&](const Forcing &f, int k) {
-        return p_at_src(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0],
-                        src_at(f, (int)col, grow(row_of(k))), f.s);
+        return p_at(Xl + NW * k * XW, Yl + NW * k * YW, km[k - Q0],
+                    src_at(f, (int)col, grow(row_of(k))), f.s);
     };
     walk(IQ0(), IQ1(), [&](int k) { const int r = row_of(k); return r >= -H && r < TY + H; },
          [&](int k) {
