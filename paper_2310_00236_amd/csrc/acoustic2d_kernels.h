@@ -185,13 +185,21 @@ __device__ __forceinline__ void update_one(typename Word<S, COMP>::type &w, floa
 }
 
 // Updates of V cells whose compensation terms are 8-bit words q (held next
-// to the values, see update_store8).
+// to the values, see update_store8); fp16 cells in pairs on packed
+// instructions (update_pair8_f16), a last odd cell alone.
 template <class S, int V>
 __device__ __forceinline__ void update_cells8(Cells<typename S::store_t, V> &c,
                                               int8_t (&q)[V], const float (&inc)[V])
 {
+    constexpr int NP = S::id == F16::id ? V / 2 : 0;
+    if constexpr (NP > 0) {
 #pragma unroll
-    for (int i = 0; i < V; ++i)
+        for (int i = 0; i < NP; ++i)
+            update_pair8_f16(c.w[2 * i], q[2 * i], c.w[2 * i + 1], q[2 * i + 1], inc[2 * i],
+                             inc[2 * i + 1]);
+    }
+#pragma unroll
+    for (int i = 2 * NP; i < V; ++i)
         update_store8<S>(c.w[i], q[i], inc[i]);
 }
 

@@ -396,9 +396,10 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     // Visits the register slots [K0, K1) whose rows pass on(k).  For fp16
     // words, where two neighbouring slots both do, their increments are
     // computed first and the two words updated together on packed
-    // instructions (update_pair: the same bits as two single updates);
-    // otherwise slot by slot.  fin(k) follows each slot's update.
-    constexpr bool PAIR = S::id == F16::id && !C8;
+    // instructions (update_pair, update_pair8_f16: the same bits as two
+    // single updates); otherwise slot by slot.  fin(k) follows each slot's
+    // update.
+    constexpr bool PAIR = S::id == F16::id;
     auto walk = [&](auto k0c, auto k1c, auto on, auto inc, auto wd, auto qb, auto fin) {
         constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
         if constexpr (PAIR) {
@@ -408,7 +409,10 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
                 const bool a = on(k), b = k + 1 < K1 && on(k1);
                 if (a && b) {
                     const float i0 = inc(k), i1 = inc(k1);
-                    update_pair<S, COMP>(wd(k), wd(k1), i0, i1);
+                    if constexpr (C8)
+                        update_pair8_f16(wd(k), qb(k), wd(k1), qb(k1), i0, i1);
+                    else
+                        update_pair<S, COMP>(wd(k), wd(k1), i0, i1);
                     fin(k);
                     fin(k1);
                 } else {

@@ -293,19 +293,18 @@ __device__ __forceinline__ double block_sum_f64(double v, double *red)
 // Biased exponent field of s, and whether s is finite.
 __device__ __forceinline__ uint32_t exp_field(_Float16 s)
 {
-    return (__builtin_bit_cast(uint16_t, s) >> 10) & 0x1fu;
+    return __builtin_amdgcn_ubfe((uint32_t)__builtin_bit_cast(uint16_t, s), 10, 5);
 }
 __device__ __forceinline__ uint32_t exp_field_bf16(uint16_t s)
 {
-    return (s >> 7) & 0xffu;
+    return __builtin_amdgcn_ubfe((uint32_t)s, 7, 8);
 }
 
 // One step of q is ulp(s) / 2^7, with ulp(s) = 2^(max(E,1) - 25) for fp16
 // (E the exponent field; E = 0 gives the subnormal spacing 2^-24) and
-// 2^(max(E,1) - 134) for bf16.  For fp16 the power of two and its inverse
-// are normal fp32 numbers, built from their exponent fields; for bf16 they
-// can leave the fp32 range, so the scaling goes through ldexpf.  Either
-// way the scaling is exact.
+// 2^(max(E,1) - 134) for bf16.  For fp16 the power of two is a normal fp32
+// number, built from its exponent field; for bf16 it can leave the fp32
+// range, so the scaling goes through ldexpf.  Either way it is exact.
 template <class S>
 __device__ __forceinline__ float comp8_decode(int8_t q, typename S::store_t s)
 {
@@ -318,35 +317,46 @@ __device__ __forceinline__ float comp8_decode(int8_t q, typename S::store_t s)
     }
 }
 
-template <class S>
-__device__ __forceinline__ float comp8_scale_up(float t, typename S::store_t s)
-{
-    if constexpr (S::id == F16::id) {
-        const uint32_t e = max(exp_field(s), 1u);
-        return t * __uint_as_float((159u - e) << 23);          // t 2^(32 - e)
-    } else {
-        const int e = (int)max(exp_field_bf16(s), 1u);
-        return ldexpf(t, 141 - e);
-    }
-}
-
-template <class S>
-__device__ __forceinline__ bool comp8_finite(typename S::store_t s)
-{
-    if constexpr (S::id == F16::id)
-        return exp_field(s) != 0x1fu;
-    else
-        return exp_field_bf16(s) != 0xffu;
-}
-
 // q = round(t / ulp(s) * 2^7), ties to even; 0 when s or t is not finite
 // (an operation of the sum overflowed).  |t| <= ulp(s)/2 keeps |q| <= 64.
+//
+// t is the error of the six-operation sum s = v + y, and only t is tested:
+// when s is not finite t is NaN (s is NaN, or s - y or s - pa subtracts two
+// infinities of one sign), so a finite t implies a finite s.
+//
+// x = t / ulp(s) * 2^7 is rounded by one addition of 1.5 * 2^m, m the
+// fraction bits of the format the addition is done in: the spacing there
+// is 1, so the round-to-nearest-even sum is round(x) + 1.5 * 2^m exactly,
+// and its low byte is round(x) in two's complement.  For fp16 the scaling
+// and the addition are fp16 operations: x has at most 11 significant bits,
+// |x| <= 64 and no bit below 2^-22, so it is exact in fp16.  For bf16 they
+// are fp32 operations (an x below the fp32 range rounds to 0 either way).
+// No branch either way.
+__device__ __forceinline__ _Float16 comp8_scaled_f16(_Float16 t, _Float16 s)
+{
+    const int e = (int)max(exp_field(s), 1u);
+    return __builtin_amdgcn_ldexph(t, 32 - e);                     // t 2^(32 - e)
+}
+__device__ __forceinline__ int8_t comp8_pick_f16(_Float16 r, _Float16 t)
+{
+    const int8_t q = (int8_t)(__builtin_bit_cast(uint16_t, r) & 0xffu);
+    return __builtin_isfinite(t) ? q : (int8_t)0;
+}
+constexpr float kRound16 = 1536.0f;          // 1.5 * 2^10
+constexpr float kRound32 = 12582912.0f;      // 1.5 * 2^23
+
 template <class S>
 __device__ __forceinline__ int8_t comp8_encode(float t, typename S::store_t s)
 {
-    if (!comp8_finite<S>(s) || !isfinite(t))
-        return 0;
-    return (int8_t)(int)rintf(comp8_scale_up<S>(t, s));
+    if constexpr (S::id == F16::id) {
+        const _Float16 th = (_Float16)t;                            // t is an fp16 value
+        return comp8_pick_f16(comp8_scaled_f16(th, s) + (_Float16)kRound16, th);
+    } else {
+        const int e = (int)max(exp_field_bf16(s), 1u);
+        const float r = ldexpf(t, 141 - e) + kRound32;
+        const int8_t q = (int8_t)(__float_as_uint(r) & 0xffu);
+        return __builtin_isfinite(t) ? q : (int8_t)0;
+    }
 }
 
 // The compensated update with the 8-bit word: y = RN(inc + t_old), the
@@ -363,7 +373,7 @@ __device__ __forceinline__ void update_store8(typename S::store_t &v, int8_t &q,
         const _Float16 da = v - pa;
         const _Float16 db = y - pb;
         const _Float16 t = da + db;
-        q = comp8_encode<S>((float)t, s);
+        q = comp8_pick_f16(comp8_scaled_f16(t, s) + (_Float16)kRound16, t);
         v = s;
     } else {
         const float vf = S::load(v);
@@ -377,6 +387,34 @@ __device__ __forceinline__ void update_store8(typename S::store_t &v, int8_t &q,
         v = S::store(s);
         q = comp8_encode<S>(t, v);
     }
+}
+
+// Two independent fp16 cells at once: the two narrowings of the right-hand
+// sides are one packed conversion, the two six-operation sums and the two
+// rounding additions packed half-precision instructions.  Lane by lane these
+// are the operations of update_store8, each correctly rounded, so the bits
+// are those of two single updates.
+__device__ __forceinline__ void update_pair8_f16(_Float16 &v0, int8_t &q0, _Float16 &v1,
+                                                 int8_t &q1, float inc0, float inc1)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2 a = {inc0 + comp8_decode<F16>(q0, v0), inc1 + comp8_decode<F16>(q1, v1)};
+    __asm__("" : "+v"(a));        // no fusing into the narrowing (see opaque)
+    const h2 y = __builtin_convertvector(a, h2);
+    const h2 v = {v0, v1};
+    const h2 s = v + y;
+    const h2 pa = s - y;
+    const h2 pb = s - pa;
+    const h2 da = v - pa;
+    const h2 db = y - pb;
+    const h2 t = da + db;
+    const h2 x = {comp8_scaled_f16(t[0], s[0]), comp8_scaled_f16(t[1], s[1])};
+    const h2 r = x + h2{(_Float16)kRound16, (_Float16)kRound16};
+    q0 = comp8_pick_f16(r[0], t[0]);
+    q1 = comp8_pick_f16(r[1], t[1]);
+    v0 = s[0];
+    v1 = s[1];
 }
 
 // The same with an fp64 increment (stencil in fp64).

@@ -96,6 +96,41 @@ def test_sizes_and_tiles(shape, tile):
     assert_bitexact(gc, wc, f"{shape} tile {tile} comps")
 
 
+@pytest.mark.parametrize("storage,scale", [("f16", 1100.0), ("bf16", 2.0 ** 116)])
+@pytest.mark.parametrize("tile", [0] + [t for t in TILE_KINDS if hw.tiles("acoustic2d")[t][2] == 2])
+def test_overflow_matches_oracle(storage, scale, tile):
+    """Two steps from pressures large enough that, in a soft medium, many
+    sums round past the largest finite value to infinity and infinities of
+    opposite sign make NaNs; the 8-bit word of a cell whose sum is not finite
+    is 0.
+    The GPU has the oracle's infinities, NaN cells, finite values and
+    compensation terms bit for bit (only a NaN's sign and payload are left
+    open), on the one-step shape and every two-step shape."""
+    nx, ny = 70, 40
+    rng = np.random.default_rng(112)
+    # a soft medium (c = 0.01) at its stable time step: the velocity
+    # increments are about 30 times the pressure differences
+    rho, kappa = np.ones((ny, nx)), np.full((ny, nx), 1e-4)
+    dt = 0.4 * hw.cfl_bound("acoustic2d", 4) / 1e-2
+    f = {"p": scale * rng.uniform(-1.0, 1.0, (ny, nx)),
+         "vx": np.zeros((ny, nx)), "vy": np.zeros((ny, nx))}
+    p = _plan(nx, ny, 4, storage, dt, rho, kappa, f, tile=tile)
+    p.advance(2)
+    g, gc = p.get_fields(comps=True)
+    p.close()
+    w, wc, _ = _oracle(nx, ny, 4, storage, dt, rho, kappa, f, 2)[:3]
+    for got, want in ((g, w), (gc, wc)):
+        for k in want:
+            gn, wn = np.isnan(got[k]), np.isnan(want[k])
+            assert np.array_equal(gn, wn), k
+            assert np.array_equal(got[k][~gn], want[k][~wn]), k
+            assert np.array_equal(np.signbit(got[k][~gn]), np.signbit(want[k][~wn])), k
+    for k in g:                                          # every case occurs
+        assert np.isinf(g[k]).any() and np.isfinite(g[k]).any(), k
+        assert np.any(gc[k][np.isfinite(g[k])] != 0), k
+    assert np.isnan(g["p"]).any()
+
+
 @pytest.mark.parametrize("stencil", ["f32", "storage", "f64"])
 def test_with_source_receivers_and_stencils(stencil):
     nx, ny = 150, 37
