@@ -59,6 +59,19 @@ __device__ __forceinline__ const lds_f *lds_base(const float *p)
     return q;
 }
 
+// A pointer that is the same in every lane, read into scalar registers
+// (the row bases of the interior tiles' loads; the compiler cannot always
+// see that they are uniform, for instance when the descriptor comes from a
+// batch table indexed at run time).
+template <class T>
+__device__ __forceinline__ const T HW_GLOBAL *scalar(const T HW_GLOBAL *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const T HW_GLOBAL *)(((uint64_t)hi << 32) | lo);
+}
+
 // A compile-time slot bound passed to a generic lambda.
 template <int N> struct IC {
     static constexpr int value = N;
@@ -147,6 +160,18 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     // this lane's grid column (unsigned: a row pointer in scalar registers
     // plus a 32-bit lane offset is one addressing mode)
     const unsigned col = (unsigned)gcol(ln);
+    // the element of tile row r in this lane's column of array a: in interior
+    // tiles the row and the tile's first column make a base in scalar
+    // registers (read there explicitly: otherwise the compiler folds the lane
+    // into a 64-bit vector base and adds each row to it) and the lane is the
+    // load's offset, so no load needs vector address arithmetic
+    auto row_at = [&](auto a, int r) {
+        if constexpr (EDGE) {
+            return (a + grow(r) * pitch)[col];
+        } else {
+            return tb::scalar(a + ((y0 + r) * pitch + x0))[(unsigned)ln];
+        }
+    };
     // point source and receivers of step n (first) and n+1 (second step)
     const Forcing f0 = FRC ? forcing(d, 0) : Forcing{false, 0.0f, 0, 0, 0, 0};
     const Forcing f1 = FRC ? forcing(d, 1) : Forcing{false, 0.0f, 0, 0, 0, 0};
@@ -208,24 +233,23 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = P0; k < P1; ++k) {
         const int r = row_of(k);
         if (r >= -2 * H && r < TY + 2 * H)
-            pw[k - P0] = (p_in + grow(r) * pitch)[col];
+            pw[k - P0] = row_at(p_in, r);
     }
 #pragma unroll
     for (int k = B0; k < B1; ++k) {
         const int r = row_of(k);
         if (r >= -G && r < TY + G)
-            bm[k - B0] = (b + grow(r) * pitch)[col];
+            bm[k - B0] = row_at(b, r);
     }
 #pragma unroll
     for (int k = Q0; k < Q1; ++k) {
         const int r = row_of(k);
         if (r >= -H && r < TY + H) {
-            const int q = grow(r) * pitch;
-            xw[k - Q0] = (vx_in + q)[col];
-            km[k - Q0] = (kap + q)[col];
+            xw[k - Q0] = row_at(vx_in, r);
+            km[k - Q0] = row_at(kap, r);
             if constexpr (C8) {
-                qxw[k - Q0] = (qx_in + q)[col];
-                qpw[k - Q0] = (qp_in + q)[col];
+                qxw[k - Q0] = row_at(qx_in, r);
+                qpw[k - Q0] = row_at(qp_in, r);
             }
         }
     }
@@ -233,10 +257,9 @@ __device__ __forceinline__ void ac2d_tile2(const Ac2dDesc &d, int par, int x0, i
     for (int k = V0; k < V1; ++k) {
         const int r = row_of(k);
         if (r >= -G && r < TY + H + R - 1) {
-            const int q = grow(r) * pitch;
-            yw[k - V0] = (vy_in + q)[col];
+            yw[k - V0] = row_at(vy_in, r);
             if constexpr (C8)
-                qyw[k - V0] = (qy_in + q)[col];
+                qyw[k - V0] = row_at(qy_in, r);
         }
     }
     if (xh_on) {
