@@ -312,6 +312,17 @@ class Plan:
     def set_tile(self, tile: int):
         _check(lib().hw_plan_set_tile(self.handle, tile))
 
+    def set_tuned_tile(self) -> int:
+        """Set the kernel shape the tuning table holds for this plan's
+        physics, order, storage, compensation and size, and return it (a
+        new plan runs shape 0, the one-step kernel; the tuned 2D shapes
+        advance two steps per launch).  Every shape gives the same bits."""
+        from . import tuning
+        pb = self.pb
+        t = tuning.best_tile(pb.physics, pb.order, pb.storage, pb.comp, pb.nx, pb.ny, pb.nz)
+        self.set_tile(t)
+        return t
+
     def export_state(self, stream=None) -> bytes:
         n = ctypes.c_size_t()
         _check(lib().hw_state_size(self.handle, ctypes.byref(n)))

@@ -170,9 +170,7 @@ class GpuExecutor:
     def __init__(self, device="cuda:0", energy_every: int = 0):
         import torch
         import paper_2310_00236_amd as hw
-        from paper_2310_00236_amd import tuning
         self.hw = hw
-        self.tuning = tuning
         self.torch = torch
         self.device = torch.device(device)
         self.copy = torch.cuda.Stream(self.device)
@@ -200,8 +198,7 @@ class GpuExecutor:
         payload = job.payload() if callable(job.payload) else job.payload
         pb, material, fields = payload
         plan = self.hw.Plan(pb, device=self.device)
-        plan.set_tile(self.tuning.best_tile(pb.physics, pb.order, pb.storage,
-                                            pb.comp, pb.nx, pb.ny, pb.nz))
+        plan.set_tuned_tile()
         plan.set_material(material, stream=self.copy)
         plan.set_fields(fields, stream=self.copy)
         self.plans[job.id] = plan

@@ -177,6 +177,36 @@ def test_simulate_matches_plan_api():
     assert np.array_equal(e, ge)
 
 
+@pytest.mark.parametrize("physics,storage,comp", [("acoustic2d", "f16", "twosum"),
+                                                   ("acoustic2d", "f16", "twosum8"),
+                                                   ("elastic3d", "f32", "none")])
+def test_tuned_tile_matches_default_shape(physics, storage, comp):
+    """Plan.set_tuned_tile() sets the tuning table's shape for the plan and
+    returns it; the run is bit-identical to the default shape's."""
+    from paper_2310_00236_amd import tuning
+    plans = []
+    for tuned in (False, True):
+        if physics == "acoustic2d":
+            p = _acoustic_plan(300, 130, storage, comp, 905)
+        else:
+            p = _elastic_plan(20, storage, comp, 906)
+        if tuned:
+            t = p.set_tuned_tile()
+            pb = p.pb
+            assert t == tuning.best_tile(pb.physics, pb.order, pb.storage, pb.comp,
+                                         pb.nx, pb.ny, pb.nz)
+            if physics == "acoustic2d":
+                assert hw.tiles(physics)[t][2] == 2          # two steps per launch
+        p.advance(21, energy_every=7)
+        plans.append((p.get_fields(comps=True), p.energy_trace()[0]))
+        p.close()
+    (g0, c0), e0 = plans[0]
+    (g1, c1), e1 = plans[1]
+    assert_bitexact(g1, g0, "tuned shape")
+    assert_bitexact(c1, c0, "tuned shape comps")
+    assert np.array_equal(e1, e0)
+
+
 def test_validation_errors_on_device_plan():
     nx = ny = 16
     rho = np.ones((ny, nx))
