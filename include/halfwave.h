@@ -291,7 +291,10 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  *               passes (velocities, then stresses); one tx by ty tile per
  *               workgroup.
  * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
- * results.  Plans with HW_COMP_TWOSUM8 take every kind but 1 (HW_E_INVAL);
+ * results.  A new plan (and hw_simulate) runs shape 0; the faster shapes
+ * are picked per size by the Python package's tuning table (for acoustic2d
+ * the two-step kinds at every size measured).  Plans with HW_COMP_TWOSUM8
+ * take every kind but 1 (HW_E_INVAL);
  * in hw_batch_advance a kind-1 tile argument runs their group on shape 0.
  * Any of the output pointers may be NULL. */
 int32_t hw_tile_count(int32_t physics);
