@@ -291,9 +291,11 @@ hw_status hw_state_import(hw_plan *plan, const void *blob, size_t bytes,
  *               passes (velocities, then stresses); one tx by ty tile per
  *               workgroup.
  * hw_plan_set_tile picks one for a plan; every shape gives bit-identical
- * results.  A new plan (and hw_simulate) runs shape 0; the faster shapes
- * are picked per size by the Python package's tuning table (for acoustic2d
- * the two-step kinds at every size measured).  Plans with HW_COMP_TWOSUM8
+ * results.  A new plan runs shape 0; the faster shapes are picked per size
+ * by the Python package's tuning table (for acoustic2d the two-step kinds
+ * at every size measured).  hw_simulate and hw_simulate_noalloc run the
+ * two-step 64 x 24 shape (acoustic2d), the fused 64 x 6 x 128 shape
+ * (elastic3d) or shape 0 (elastic2d).  Plans with HW_COMP_TWOSUM8
  * take every kind but 1 (HW_E_INVAL);
  * in hw_batch_advance a kind-1 tile argument runs their group on shape 0.
  * Any of the output pointers may be NULL. */
@@ -319,7 +321,8 @@ hw_status hw_batch_advance(hw_plan *const *plans, int32_t n,
 /* Blocking convenience: create a plan in the arena, upload material and
  * fields, advance nsteps with the energy every energy_every steps, download
  * the fields into the same arrays (fields must be non-NULL host arrays) and
- * copy up to energy_cap energies.  *n_energy receives the trace length. */
+ * copy up to energy_cap energies.  *n_energy receives the trace length.
+ * The plan runs the shape stated above hw_tile_count. */
 hw_status hw_simulate(const hw_problem *pb, const double *const *material,
                       double *const *fields, int64_t nsteps,
                       int64_t energy_every, double *energy, int64_t energy_cap,
