@@ -207,6 +207,38 @@ def test_tuned_tile_matches_default_shape(physics, storage, comp):
     assert np.array_equal(e1, e0)
 
 
+@pytest.mark.parametrize("physics,storage,comp", [("acoustic2d", "f16", "twosum8"),
+                                                   ("elastic3d", "f16", "twosum"),
+                                                   ("elastic3d", "bf16", "none")])
+def test_simulate_matches_oracle(physics, storage, comp):
+    """hw_simulate (two-step 2D shape, fused 3D shape) against the oracle
+    directly, with an odd step count."""
+    if physics == "acoustic2d":
+        nx, ny, nz = 131, 45, 1
+        rho, kappa, c = layered_material(nx, ny, 907)
+        dt = 0.4 * hw.cfl_bound(physics, 4) / c
+        f = acoustic_fields(nx, ny, 908, storage)
+        mat = [rho, kappa]
+        pb = hw.Problem(physics, nx, ny, nz, 4, storage, comp, 1.0, dt, 0, 8)
+    else:
+        nx, ny, nz = 17, 12, 21
+        rho, lam, mu, cp = smooth_medium3d(nx, ny, nz, 909)
+        dt = 0.4 * hw.cfl_bound(physics, 2) / cp
+        f = elastic_fields(nx, ny, nz, 910)
+        mat = [rho, lam, mu]
+        pb = hw.Problem(physics, nx, ny, nz, 2, storage, comp, 1.0, dt, 0, 8)
+    out, e = hw.simulate(pb, mat, f, 23, energy_every=11)
+    if physics == "acoustic2d":
+        w, _, we = oracle_acoustic(nx, ny, 4, storage, comp, dt, rho, kappa, f, 23,
+                                   energy_every=11)[:3]
+    else:
+        from helpers import oracle_elastic
+        w, _, we = oracle_elastic(nx, ny, nz, storage, comp, dt, rho, lam, mu, f, 23,
+                                  energy_every=11)[:3]
+    assert_bitexact(out, w, "simulate")
+    np.testing.assert_allclose(e, we, rtol=1e-12, atol=0)
+
+
 def test_validation_errors_on_device_plan():
     nx = ny = 16
     rho = np.ones((ny, nx))
